@@ -1,0 +1,81 @@
+"""Pins of the oracle's 16-bit storage emulation.
+
+The rounding of FP32 to binary16 and to bfloat16 is pinned bit-exactly
+against two library routines (numpy's float16 cast and torch's bfloat16 cast,
+both round-to-nearest-even); the FP32 arithmetic of the emulated time loop is
+pinned against the NumPy twin's independent emulation."""
+import numpy as np
+import pytest
+import torch
+
+import fd_inputs as fi
+from oracle import np_twin
+
+
+def _probe_values():
+    rng = np.random.default_rng(0)
+    parts = [
+        rng.standard_normal(20000).astype(np.float32) * np.float32(10.0) ** rng.integers(-9, 6, 20000).astype(np.float32),
+        np.array([0.0, -0.0, 1.0, -1.0, 65504.0, 65519.99, 65520.0, 1e6, -1e6, np.inf, -np.inf,
+                  2.0 ** -14, 2.0 ** -24, 2.0 ** -25, 2.0 ** -25 * 1.0000001, 2.0 ** -26, 1e-30,
+                  3.0 * 2.0 ** -26, 2.0 ** -15 + 2.0 ** -25], dtype=np.float32),
+    ]
+    # exact ties for binary16 normals (bit 12 set, lower bits clear) and bf16
+    u = rng.integers(0x38800000, 0x477F0000, 5000, dtype=np.uint32)
+    parts.append(((u & ~np.uint32(0x1FFF)) | np.uint32(0x1000)).view(np.float32))
+    parts.append(((u & ~np.uint32(0xFFFF)) | np.uint32(0x8000)).view(np.float32))
+    # subnormal-range binary16 values
+    parts.append(rng.uniform(-2.0 ** -14, 2.0 ** -14, 5000).astype(np.float32))
+    return np.concatenate(parts).astype(np.float32)
+
+
+def test_f16_rounding_matches_numpy(orc):
+    x = _probe_values()
+    got = orc.encode(1, x)
+    ref = x.astype(np.float16).view(np.uint16)
+    np.testing.assert_array_equal(got, ref)
+    back = orc.decode(1, ref)
+    np.testing.assert_array_equal(back, ref.view(np.float16).astype(np.float32))
+
+
+def test_bf16_rounding_matches_torch(orc):
+    x = _probe_values()
+    x = x[np.isfinite(x)]
+    got = orc.encode(2, x)
+    ref = torch.from_numpy(x).to(torch.bfloat16).view(torch.int16).numpy().view(np.uint16)
+    np.testing.assert_array_equal(got, ref)
+    back = orc.decode(2, ref)
+    np.testing.assert_array_equal(
+        back, torch.from_numpy(ref.view(np.int16)).view(torch.bfloat16).float().numpy())
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_half_emulation_matches_twin(orc, storage, ndim):
+    if ndim == 2:
+        p = fi.surface2d(26, 30, 70, seed=8).scaled(sponge_width=4, sponge_alpha=0.06)
+    else:
+        p = fi.layered3d(nx=14, ny=13, nz=12, nt=40)
+    v = fi.random_velocity(p.shape, 17)
+    shp = (p.nz, p.ny, p.nx)
+    out = orc.forward_half(orc.grid_of(p), storage, v.reshape(shp), p.wavelet(), p.nt, p.src,
+                           p.rec_index())
+    tr, cur = np_twin.Twin(p, v).forward_half(p.wavelet(), p.nt, storage)
+    # Same FP32 operation order and rounding on both sides: bit-identical.
+    np.testing.assert_array_equal(out["traces"], tr)
+    np.testing.assert_array_equal(out["cur"].reshape(cur.shape), cur)
+
+
+@pytest.mark.parametrize("storage,bound", [(1, 2e-3), (2, 3e-2)])
+def test_half_error_against_fp64_is_bounded(orc, storage, bound):
+    p = fi.surface2d(48, 52, 150, seed=9)
+    v = fi.random_velocity(p.shape, 18, 2000, 3500)
+    shp = (p.nz, 1, p.nx)
+    g = orc.grid_of(p)
+    ref = orc.forward(g, v.reshape(shp), p.wavelet(), p.nt, p.src, p.rec_index())
+    out = orc.forward_half(g, storage, v.reshape(shp), p.wavelet(), p.nt, p.src, p.rec_index())
+    e_tr = orc.rel_l2(out["traces"], ref["traces"])
+    e_f = orc.rel_l2(out["cur"], ref["cur"])
+    assert e_tr <= bound and e_f <= bound, (e_tr, e_f)
+    # 16-bit storage must cost more than FP32 rounding alone
+    assert e_f > 1e-6
