@@ -1,0 +1,219 @@
+/*
+ * fd.h - C ABI of the MI355X (gfx950) finite-difference acoustic wave engine.
+ *
+ * The library advances the acoustic wave equation of arXiv 2311.05038,
+ * Section 7, Eq. 1 (P_tt = v^2 (P_xx + P_zz) + S(t)), in 2D (z, x) and in 3D
+ * (z, y, x), by explicit finite differences: one time step is the sequence
+ * of Listing 3 (source addition to P, second derivatives along each axis,
+ * time update to Pnew, rotation of Pold/P/Pnew), fused here into one kernel
+ * per step.  Readings of what the paper leaves open:
+ *   - second derivatives: 8th-order central weights (radius R = 4)
+ *     a = (-205/72, 8/5, -1/5, 8/315, -1/560); taps outside the grid read 0;
+ *   - one grid spacing dh on every axis (the paper's single dh); the
+ *     velocity term c = (v dt / dh)^2;
+ *   - the source adds dt^2 / dh^D * s[n] to one cell of P before the
+ *     derivatives (S sits outside v^2 in Eq. 1);
+ *   - damping band ("sponge"): new = G (2 P + c L P) - G^2 Pold, with
+ *     G = gz(z) gy(y) gx(x), g(i) = exp(-(alpha d)^2) and d the distance
+ *     into the band of an enabled face;
+ *   - receivers sample the new field of each step before the next source
+ *     addition: traces[n][r] = Pnew_n[cell r].
+ *
+ * Conventions.
+ *   - Every function returns an fd_status; nothing throws across the ABI.
+ *     A non-OK status leaves outputs untouched unless stated, and
+ *     fd_last_error() gives a message (thread-local, valid until the next
+ *     call on that thread).
+ *   - "device" pointers are HIP device (HBM) addresses; "host" pointers are
+ *     ordinary process memory.  The library never allocates device memory:
+ *     the caller provides every buffer, sized by fd_query_bytes.  Handles
+ *     (fd_model, fd_state) are small host objects owned by the library,
+ *     released by the matching destroy call; they borrow the caller's
+ *     device buffers, which must outlive them.
+ *   - `stream` is a hipStream_t (NULL = the default stream).  Calls enqueue
+ *     work on it and return without waiting, except fd_create_model, which
+ *     waits for its own work (it reads the velocity range back).
+ *   - Dense arrays that cross the ABI are row-major [nz][ny][nx] (ny = 1 in
+ *     2D), x fastest, FP32 unless stated.  Internal buffers use a private
+ *     padded layout and are only read or written through this API.
+ *   - Work on one fd_state must stay on one stream; an fd_model may be used
+ *     from several streams at once.
+ */
+#ifndef FD_H
+#define FD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    FD_OK = 0,
+    FD_ERR_INVALID_ARG = 1,   /* null pointer, out-of-range size/index, buffer too small */
+    FD_ERR_UNSTABLE = 2,      /* velocity/time step violate the stability bound */
+    FD_ERR_OUT_OF_MEMORY = 3, /* host allocation of a handle failed */
+    FD_ERR_DEVICE = 4,        /* a HIP call or kernel launch failed */
+    FD_ERR_UNSUPPORTED = 5    /* valid request this build does not implement */
+} fd_status;
+
+typedef enum { FD_F32 = 0, FD_F16 = 1, FD_BF16 = 2 } fd_storage;
+typedef enum { FD_BC_ZERO = 0, FD_BC_PERIODIC = 1 } fd_bc;
+
+/* Sponge face bits. */
+#define FD_FACE_ZLO 0x01u
+#define FD_FACE_ZHI 0x02u
+#define FD_FACE_YLO 0x04u
+#define FD_FACE_YHI 0x08u
+#define FD_FACE_XLO 0x10u
+#define FD_FACE_XHI 0x20u
+
+/* Largest batch accepted by fd_step_batch. */
+#define FD_BATCH_MAX 16
+
+/* The computational grid and its discretisation (Section 7: dh, dt). */
+typedef struct {
+    int32_t ndim;          /* 2 or 3 */
+    int32_t radius;        /* stencil half-width; this build: 4 */
+    int32_t bc;            /* fd_bc; this build: FD_BC_ZERO */
+    int32_t sponge_width;  /* cells in the damping band, 0 = none */
+    int64_t nz, ny, nx;    /* cells; ny must be 1 when ndim == 2 */
+    double dh;             /* grid spacing, m (> 0) */
+    double dt;             /* time step, s (> 0) */
+    double sponge_alpha;   /* damping constant; <= 0 selects 0.3 / sponge_width */
+    uint32_t sponge_faces; /* FD_FACE_* bits of the faces that damp */
+    int32_t storage;       /* fd_storage of the wavefields (arithmetic is FP32) */
+} fd_grid;
+
+/* A regular receiver array: cells (z0 + i*dz, y0 + j*dy, x0 + k*dx) for
+ * i < nz, j < ny, k < nx; receiver r = (i*ny + j)*nx + k.  nz = ny = nx = 0
+ * means no receivers.  Every cell must lie inside the grid (y0 = 0, ny = 1
+ * in 2D). */
+typedef struct {
+    int64_t z0, y0, x0;
+    int64_t nz, ny, nx;
+    int64_t dz, dy, dx;
+} fd_receivers;
+
+/* One shot: a point source and its wavelet, plus the receivers. */
+typedef struct {
+    int64_t src_z, src_y, src_x; /* source cell (src_y = 0 in 2D) */
+    const float *wavelet;        /* device, nt samples s[0..nt-1] (Eq. 1's S(t) at t = n dt) */
+    int64_t nt;                  /* time steps of the shot (>= 1) */
+    fd_receivers rec;
+} fd_shot;
+
+/* Device bytes the caller provides. */
+typedef struct {
+    size_t model;        /* fd_create_model's buffer */
+    size_t state;        /* fd_create_state's buffer (two time levels) */
+    size_t checkpoints;  /* fd_run_shot's checkpoint buffer for (nt, ckpt_every) */
+    size_t adjoint_work; /* fd_adjoint_gradient's work buffer for ckpt_every */
+} fd_sizes;
+
+typedef struct fd_model fd_model;
+typedef struct fd_state fd_state;
+
+/* Bytes of every caller-provided buffer for this grid.  nt and ckpt_every
+ * only affect `checkpoints` and `adjoint_work` (pass 0 to skip them).
+ * Host-only; no device work. */
+fd_status fd_query_bytes(const fd_grid *grid, int64_t nt, int32_t ckpt_every, fd_sizes *out);
+
+/* Model setup (velocity V, dt, dh of Listing 3's WaveSimulator): computes
+ * c = (v dt / dh)^2 and the damping profiles into `model_buf` (device,
+ * >= fd_sizes.model bytes), then checks stability
+ *     (vmax dt / dh)^2 * ndim * 6.5015873 <= 4
+ * (the largest magnitude of the 8th-order second-difference symbol is
+ * 4096/630), returning FD_ERR_UNSTABLE if it fails and FD_ERR_INVALID_ARG if
+ * some velocity is not a positive finite number.  `velocity` is device,
+ * dense FP32 m/s, read only during this call.  Synchronises `stream`. */
+fd_status fd_create_model(const fd_grid *grid, const float *velocity, void *model_buf,
+                          size_t model_bytes, void *stream, fd_model **out);
+fd_status fd_destroy_model(fd_model *model);
+
+/* Binds a state (the two time levels P and Pold) to `state_buf` (device,
+ * >= fd_sizes.state bytes).  Host-only; call fd_begin_shot before stepping. */
+fd_status fd_create_state(const fd_model *model, void *state_buf, size_t state_bytes,
+                          fd_state **out);
+fd_status fd_destroy_state(fd_state *state);
+
+/* Puts the state at rest and performs the first source addition
+ * (P[src] = dt^2/dh^D * s[0]).  The next step is n = 0. */
+fd_status fd_begin_shot(const fd_model *model, fd_state *state, const fd_shot *shot,
+                        void *stream);
+
+/* Time step n (must be the state's next step, 0 <= n < shot->nt): the
+ * derivatives and time update of Listing 3 on P, then trace_row[r] =
+ * Pnew[rec r] (device, nrec floats, or NULL), then the source addition of
+ * step n+1 (none after the last step), then the rotation of levels.
+ * fd_step n = 0..nt-1 after fd_begin_shot equals fd_run_shot bit for bit. */
+fd_status fd_step(const fd_model *model, fd_state *state, const fd_shot *shot, int64_t n,
+                  float *trace_row, void *stream);
+
+/* A whole shot: fd_begin_shot then steps 0..nt-1.  traces: device
+ * [nt][nrec] or NULL.  ckpt: device buffer of ckpt_bytes bytes (at least
+ * fd_sizes.checkpoints for (nt, ckpt_every)), or NULL; when given, the state
+ * before steps 0, K, 2K, ... (K = ckpt_every >= 1) is saved for
+ * fd_adjoint_gradient. */
+fd_status fd_run_shot(const fd_model *model, fd_state *state, const fd_shot *shot,
+                      float *traces, void *ckpt, size_t ckpt_bytes, int32_t ckpt_every,
+                      void *stream);
+
+/* Exact discrete adjoint of fd_run_shot: accumulates into grad_v (device,
+ * dense FP64, +=) the gradient dJ/dv of a scalar J of the traces, given
+ * adj = dJ/dtraces (device FP32 [nt][nrec]) and the checkpoints fd_run_shot
+ * saved for this model and shot with the same ckpt_every (ckpt_bytes as
+ * given to fd_run_shot).  Each checkpoint
+ * segment is recomputed, then the adjoint field is stepped backward:
+ *   z^k = G (2 z^{k+1} + c L z^{k+1}) - G^2 z^{k+2} + c G R^T adj[k-1],
+ *   dJ/dc += z^k / c * L(P^{k-1}),   dJ/dv = dJ/dc * 2 c / v,
+ * with the time sum accumulated in FP64 on the device.
+ * work: device, >= fd_sizes.adjoint_work bytes.  FP32 storage only. */
+fd_status fd_adjoint_gradient(const fd_model *model, const fd_shot *shot, const float *adj,
+                              const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every,
+                              void *work, size_t work_bytes, double *grad_v, void *stream);
+
+/* Copies P (which = 0) or Pold (which = 1) of the state, decoded to FP32,
+ * into `out` (device, dense [nz][ny][nx]).  After k steps P holds the new
+ * field of step k-1 plus the source addition of step k (none after the
+ * last step, so after a whole shot it is the final wavefield). */
+fd_status fd_get_wavefield(const fd_state *state, int32_t which, float *out, void *stream);
+
+/* Sets P (which = 0) or Pold (which = 1) of the state from `in` (device,
+ * dense FP32 [nz][ny][nx]): the "set" accessor beside fd_get_wavefield
+ * (Listing 3's WaveSimulator exposes set/get methods).  With 16-bit storage
+ * the level's scale is 2^(floor(log2 max|in|) - 11) and the values are
+ * rounded to nearest even.  On a state that has not begun a shot, the state
+ * is first put at rest with next step 0.  No source addition is made. */
+fd_status fd_set_wavefield(fd_state *state, int32_t which, const float *in, void *stream);
+
+/* One batch entry for fd_step_batch: a shot in flight with its own model,
+ * state and next step n; traces is device [nt][nrec] or NULL (row n is
+ * written). */
+typedef struct {
+    const fd_model *model;
+    fd_state *state;
+    const fd_shot *shot;
+    int64_t n;
+    float *traces;
+} fd_batch_item;
+
+/* Advances every item by up to `nsteps` steps with ONE kernel launch per
+ * step covering all items (continuous batching of shots on grids of
+ * different sizes).  An item stops at its last step; items[i].n is updated
+ * (host) to the next step of each item.  Results equal fd_step on each
+ * item alone, bit for bit.  2D, FP32 storage, count <= FD_BATCH_MAX. */
+fd_status fd_step_batch(fd_batch_item *items, int32_t count, int32_t nsteps, void *stream);
+
+/* Message for the last non-OK status on this thread ("" if none). */
+const char *fd_last_error(void);
+
+/* Library version string. */
+const char *fd_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* FD_H */

@@ -73,7 +73,7 @@ def lib():
         L.or_forward.restype = ctypes.c_int
         L.or_adjoint.argtypes = [P, P, P, i64, i64, i64, P, P, P, P]
         L.or_adjoint.restype = ctypes.c_int
-        L.or_forward_half.argtypes = [P, ctypes.c_int, P, P, i64, i64, i64, P, P, P]
+        L.or_forward_half.argtypes = [P, ctypes.c_int, P, P, i64, i64, i64, P, P, P, P, P]
         L.or_forward_half.restype = ctypes.c_int
         L.or_encode_array.argtypes = [ctypes.c_int, P, P, i64]
         L.or_decode_array.argtypes = [ctypes.c_int, P, P, i64]
@@ -172,15 +172,19 @@ def adjoint(grid: OrGrid, v: np.ndarray, wavelet: np.ndarray, nt: int, src, rec_
 
 
 def forward_half(grid: OrGrid, storage: int, v: np.ndarray, wavelet: np.ndarray, nt: int,
-                 src, rec_index):
-    """16-bit storage emulation (storage 1 = binary16, 2 = bfloat16)."""
+                 src, rec_index, init_prev=None, init_cur=None):
+    """16-bit storage emulation (storage 1 = binary16, 2 = bfloat16).
+    init_prev/init_cur (FP32) replace the start state and its s[0] addition."""
     v = np.ascontiguousarray(v, dtype=np.float32)
+    ip = None if init_prev is None else np.ascontiguousarray(init_prev, dtype=np.float32)
+    ic = None if init_cur is None else np.ascontiguousarray(init_cur, dtype=np.float32)
     wavelet = np.ascontiguousarray(wavelet, dtype=np.float32)
     rec = np.ascontiguousarray(rec_index, dtype=np.int64)
     traces = np.zeros((nt, rec.size), dtype=np.float32)
     cur = np.empty(v.shape, dtype=np.float32)
     rc = lib().or_forward_half(ctypes.byref(grid), storage, _p(v), _p(wavelet), nt,
-                               _src_linear(grid, src), rec.size, _p(rec), _p(traces), _p(cur))
+                               _src_linear(grid, src), rec.size, _p(rec), _p(ip), _p(ic),
+                               _p(traces), _p(cur))
     if rc != 0:
         raise MemoryError("oracle forward_half: allocation failed")
     return dict(traces=traces, cur=cur)

@@ -346,12 +346,15 @@ static int32_t storage_exponent(float m)
  *   e_new = floor(log2(max(M_cur, M_prev, |amp s[n+1]|))) - 11;
  *   store q = RNE16(x * 2^-e_new); M_new = max |x|.
  * The start state holds amp*s[0] at the source (stored the same way), so the
- * source addition happens once per level, as in or_forward.
+ * source addition happens once per level, as in or_forward.  Given
+ * (init_prev, init_cur) instead, the start state is those FP32 fields, each
+ * stored with exponent floor(log2 max|field|) - 11, and no s[0] is added.
  * c and G are the FP64 setup rounded to FP32, G as a product of FP32 axis
  * profiles (z, y, x order).
  */
 int or_forward_half(const or_grid *g, int storage, const float *v, const float *wavelet,
                     int64_t nt, int64_t src, int64_t nrec, const int64_t *rec,
+                    const float *init_prev, const float *init_cur,
                     float *traces, float *final_cur)
 {
     const int64_t N = g->nz * g->ny * g->nx;
@@ -392,7 +395,19 @@ int or_forward_half(const or_grid *g, int storage, const float *v, const float *
     /* start state */
     int32_t ec, ep = 0;
     float Mc, Mp = 0.0f;
-    {
+    if (init_cur || init_prev) {
+        Mc = 0.0f;
+        for (int64_t i = 0; i < N; ++i) {
+            if (init_cur && fabsf(init_cur[i]) > Mc) Mc = fabsf(init_cur[i]);
+            if (init_prev && fabsf(init_prev[i]) > Mp) Mp = fabsf(init_prev[i]);
+        }
+        ec = storage_exponent(Mc);
+        ep = storage_exponent(Mp);
+        for (int64_t i = 0; i < N; ++i) {
+            qc[i] = enc(storage, ldexpf(init_cur ? init_cur[i] : 0.0f, -ec));
+            qp[i] = enc(storage, ldexpf(init_prev ? init_prev[i] : 0.0f, -ep));
+        }
+    } else {
         float x0 = (nt > 0 && src >= 0) ? amp * wavelet[0] : 0.0f;
         ec = storage_exponent(fabsf(x0));
         if (src >= 0) qc[src] = enc(storage, ldexpf(x0, -ec));

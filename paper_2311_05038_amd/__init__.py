@@ -1,0 +1,251 @@
+"""MI355X (gfx950) finite-difference acoustic wave engine.
+
+The wave equation of arXiv 2311.05038 (Section 7, Eq. 1), stepped with the
+fused form of Listing 3's routine sequence by hand-written HIP kernels behind
+the C ABI of include/fd.h.  This module is a thin layer over that ABI: torch
+supplies device memory and streams; every step of the computation runs in
+libfd.so.  There is no CPU fallback: importing fails if the library is not
+built.
+
+    m = Model(grid_kwargs, velocity_tensor)      # fd_create_model
+    s = m.new_state()                            # fd_create_state
+    traces = m.run_shot(s, shot)                 # fd_run_shot
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _abi
+from ._abi import (FDError, FD_BF16, FD_F16, FD_F32, FD_BATCH_MAX, fd_batch_item, fd_grid,
+                   fd_receivers, fd_shot, fd_sizes)
+
+__all__ = ["Grid", "Receivers", "Shot", "Model", "State", "FDError", "FD_F32", "FD_F16",
+           "FD_BF16", "step_batch", "ensure_built"]
+
+FACES_NO_TOP = 0x3E
+
+
+def ensure_built() -> None:
+    _abi.lib()
+
+
+def _stream_handle(stream: Optional[torch.cuda.Stream] = None) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _alloc(nbytes: int, device) -> torch.Tensor:
+    """A 256-byte aligned device byte buffer (torch's caching allocator
+    returns at least 512-byte aligned blocks)."""
+    t = torch.empty(max(int(nbytes), 1), dtype=torch.uint8, device=device)
+    assert t.data_ptr() % 256 == 0
+    return t
+
+
+@dataclass
+class Grid:
+    """Grid and discretisation (fd_grid)."""
+    ndim: int
+    nz: int
+    ny: int
+    nx: int
+    dh: float
+    dt: float
+    sponge_width: int = 0
+    sponge_alpha: float = 0.0
+    sponge_faces: int = FACES_NO_TOP
+    storage: int = FD_F32
+    radius: int = 4
+    bc: int = 0
+
+    def c(self) -> fd_grid:
+        return fd_grid(ndim=self.ndim, radius=self.radius, bc=self.bc,
+                       sponge_width=self.sponge_width, nz=self.nz, ny=self.ny, nx=self.nx,
+                       dh=self.dh, dt=self.dt, sponge_alpha=self.sponge_alpha,
+                       sponge_faces=self.sponge_faces, storage=self.storage)
+
+    @property
+    def shape(self):
+        return (self.nz, self.nx) if self.ndim == 2 else (self.nz, self.ny, self.nx)
+
+    @property
+    def ncells(self) -> int:
+        return self.nz * self.ny * self.nx
+
+
+@dataclass
+class Receivers:
+    z0: int = 0
+    y0: int = 0
+    x0: int = 0
+    nz: int = 0
+    ny: int = 0
+    nx: int = 0
+    dz: int = 1
+    dy: int = 1
+    dx: int = 1
+
+    @property
+    def count(self) -> int:
+        return self.nz * self.ny * self.nx
+
+    def c(self) -> fd_receivers:
+        return fd_receivers(z0=self.z0, y0=self.y0, x0=self.x0, nz=self.nz, ny=self.ny,
+                            nx=self.nx, dz=self.dz, dy=self.dy, dx=self.dx)
+
+
+class Shot:
+    """A point source with its wavelet (device FP32 tensor) and receivers."""
+
+    def __init__(self, src, wavelet: torch.Tensor, receivers: Receivers):
+        if wavelet.dtype != torch.float32 or not wavelet.is_cuda or not wavelet.is_contiguous():
+            raise ValueError("wavelet must be a contiguous FP32 device tensor")
+        self.src = tuple(int(v) for v in src)
+        self.wavelet = wavelet
+        self.receivers = receivers
+        self.nt = int(wavelet.numel())
+        self._c = fd_shot(src_z=self.src[0], src_y=self.src[1], src_x=self.src[2],
+                          wavelet=wavelet.data_ptr(), nt=self.nt, rec=receivers.c())
+
+    @property
+    def nrec(self) -> int:
+        return self.receivers.count
+
+
+class Model:
+    """fd_create_model over torch-owned device memory."""
+
+    def __init__(self, grid: Grid, velocity: torch.Tensor, stream=None):
+        if velocity.dtype != torch.float32 or not velocity.is_cuda:
+            raise ValueError("velocity must be an FP32 device tensor")
+        if velocity.numel() != grid.ncells:
+            raise ValueError(f"velocity has {velocity.numel()} cells, grid has {grid.ncells}")
+        velocity = velocity.contiguous()
+        self.grid = grid
+        self.device = velocity.device
+        self._g = grid.c()
+        self.sizes: fd_sizes = _abi.fd_query_bytes(self._g)
+        self.buf = _alloc(self.sizes.model, self.device)
+        self.handle = _abi.fd_create_model(self._g, velocity.data_ptr(), self.buf.data_ptr(),
+                                           self.sizes.model, _stream_handle(stream))
+
+    def sizes_for(self, nt: int, ckpt_every: int) -> fd_sizes:
+        return _abi.fd_query_bytes(self._g, nt, ckpt_every)
+
+    def new_state(self) -> "State":
+        return State(self)
+
+    def run_shot(self, state: "State", shot: Shot, traces: Optional[torch.Tensor] = None,
+                 ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0,
+                 stream=None) -> torch.Tensor:
+        if traces is None:
+            traces = torch.empty((shot.nt, max(shot.nrec, 1)), dtype=torch.float32,
+                                 device=self.device)
+        _abi.fd_run_shot(self.handle, state.handle, shot._c,
+                         traces.data_ptr() if shot.nrec > 0 else None,
+                         ckpt.data_ptr() if ckpt is not None else None,
+                         ckpt.numel() if ckpt is not None else 0, ckpt_every,
+                         _stream_handle(stream))
+        state.next = shot.nt
+        return traces
+
+    def checkpoint_buffer(self, nt: int, ckpt_every: int) -> torch.Tensor:
+        return _alloc(self.sizes_for(nt, ckpt_every).checkpoints, self.device)
+
+    def adjoint_gradient(self, shot: Shot, adj: torch.Tensor, ckpt: torch.Tensor,
+                         ckpt_every: int, grad_v: torch.Tensor,
+                         work: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        if adj.dtype != torch.float32 or not adj.is_contiguous():
+            raise ValueError("adj must be contiguous FP32")
+        if grad_v.dtype != torch.float64 or grad_v.numel() != self.grid.ncells:
+            raise ValueError("grad_v must be an FP64 tensor of the grid's size")
+        need = self.sizes_for(shot.nt, ckpt_every).adjoint_work
+        if work is None:
+            work = _alloc(need, self.device)
+        _abi.fd_adjoint_gradient(self.handle, shot._c, adj.data_ptr(), ckpt.data_ptr(),
+                                 ckpt.numel(), ckpt_every, work.data_ptr(), work.numel(),
+                                 grad_v.data_ptr(), _stream_handle(stream))
+        return grad_v
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                _abi.fd_destroy_model(h)
+            except Exception:
+                pass
+            self.handle = None
+
+
+class State:
+    """fd_create_state: the two time levels of one shot in flight."""
+
+    def __init__(self, model: Model):
+        self.model = model
+        self.buf = _alloc(model.sizes.state, model.device)
+        self.handle = _abi.fd_create_state(model.handle, self.buf.data_ptr(), model.sizes.state)
+        self.next = -1
+
+    def begin(self, shot: Shot, stream=None) -> None:
+        _abi.fd_begin_shot(self.model.handle, self.handle, shot._c, _stream_handle(stream))
+        self.next = 0
+
+    def step(self, shot: Shot, n: int, trace_row: Optional[torch.Tensor] = None,
+             stream=None) -> None:
+        _abi.fd_step(self.model.handle, self.handle, shot._c, n,
+                     trace_row.data_ptr() if trace_row is not None else None,
+                     _stream_handle(stream))
+        self.next = n + 1
+
+    def wavefield(self, which: int = 0, out: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+        if out is None:
+            out = torch.empty(self.model.grid.shape, dtype=torch.float32,
+                              device=self.model.device)
+        _abi.fd_get_wavefield(self.handle, which, out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def set_wavefield(self, which: int, values: torch.Tensor, stream=None) -> None:
+        if values.dtype != torch.float32 or values.numel() != self.model.grid.ncells:
+            raise ValueError("values must be FP32 with one entry per cell")
+        values = values.contiguous()
+        _abi.fd_set_wavefield(self.handle, which, values.data_ptr(), _stream_handle(stream))
+        if self.next < 0:
+            self.next = 0
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                _abi.fd_destroy_state(h)
+            except Exception:
+                pass
+            self.handle = None
+
+
+def step_batch(entries: Sequence[tuple], nsteps: int, stream=None) -> list:
+    """fd_step_batch over (model, state, shot, traces) entries, each at its
+    state's next step.  Returns the next step of every entry."""
+    if len(entries) > FD_BATCH_MAX:
+        raise ValueError(f"at most {FD_BATCH_MAX} entries")
+    arr = (fd_batch_item * max(len(entries), 1))()
+    keep = []
+    for i, (model, state, shot, traces) in enumerate(entries):
+        arr[i].model = model.handle
+        arr[i].state = state.handle
+        arr[i].shot = ctypes.pointer(shot._c)
+        keep.append(arr[i].shot)
+        arr[i].n = state.next
+        arr[i].traces = traces.data_ptr() if traces is not None else None
+    if entries:
+        _abi.check(_abi.lib().fd_step_batch(arr, len(entries), nsteps, _stream_handle(stream)))
+    out = []
+    for i, (_, state, _, _) in enumerate(entries):
+        state.next = int(arr[i].n)
+        out.append(state.next)
+    return out

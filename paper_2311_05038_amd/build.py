@@ -1,0 +1,46 @@
+"""Builds libfd.so (the gfx950 HIP kernels and the C ABI of include/fd.h).
+
+Run as ``python -m paper_2311_05038_amd.build``; the library is written next
+to this file so that it travels with the source tree."""
+from __future__ import annotations
+
+import os
+import subprocess
+import sys
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+CSRC = os.path.join(HERE, "csrc")
+LIB = os.path.join(HERE, "libfd.so")
+SOURCES = ["fd_kernels.hip", "fd_api.cpp"]
+
+HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
+
+FLAGS = [
+    "--offload-arch=gfx950",
+    "-O3",
+    "-std=c++17",
+    "-fPIC",
+    "-shared",
+    "-ffp-contract=off",
+    # packed FP32 instructions stay off: the kernels are plain scalar FP32
+    "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    "-Wall",
+    "-Wno-unused-command-line-argument",
+]
+
+
+def build(verbose: bool = False, out: str = LIB, defines=()) -> str:
+    """Compile every source into one shared library (`out`).  `defines`
+    (e.g. ["FD_3D_ZC=32"]) override the tile-shape defaults."""
+    tmp = out + ".tmp%d" % os.getpid()
+    cmd = [HIPCC] + FLAGS + ["-D" + d for d in defines] + \
+        [os.path.join(CSRC, f) for f in SOURCES] + ["-o", tmp]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    os.replace(tmp, out)
+    return out
+
+
+if __name__ == "__main__":
+    print(build(verbose="-v" in sys.argv))

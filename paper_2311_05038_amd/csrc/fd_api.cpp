@@ -1,0 +1,571 @@
+// C ABI of the finite-difference engine: validation, buffer layouts, handle
+// management and kernel dispatch.  Declarations and semantics: include/fd.h.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/fd.h"
+#include "fd_launch.hpp"
+
+using fdk::StepArgs;
+
+namespace {
+
+thread_local std::string g_err;
+
+fd_status fail(fd_status st, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return st;
+}
+
+fd_status ok()
+{
+    g_err.clear();
+    return FD_OK;
+}
+
+fd_status hip_fail(hipError_t e, const char *what)
+{
+    return fail(FD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+constexpr size_t kAlign = 256;
+size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
+
+// Largest magnitude of the 8th-order second-difference symbol, 4096/630.
+constexpr double kSymbolMax = 4096.0 / 630.0;
+constexpr int64_t kMaxDim = (int64_t)1 << 30;
+
+struct Layout {
+    int32_t ndim, storage;
+    int64_t nz, ny, nx;
+    int32_t px;        // row pitch in elements (multiple of 64)
+    size_t npad;       // nz * ny * px
+    size_t elem;       // bytes per stored field element
+    size_t field;      // bytes of one stored field, aligned
+    size_t f32field;   // bytes of one FP32 padded field, aligned
+    size_t c_off, gz_off, gy_off, gx_off, scratch_off, model_bytes;
+    size_t state_bytes, meta_off;
+};
+
+Layout make_layout(const fd_grid &g)
+{
+    Layout L{};
+    L.ndim = g.ndim;
+    L.storage = g.storage;
+    L.nz = g.nz;
+    L.ny = g.ny;
+    L.nx = g.nx;
+    L.px = (int32_t)((g.nx + 63) / 64 * 64);
+    L.npad = (size_t)g.nz * (size_t)g.ny * (size_t)L.px;
+    L.elem = g.storage == FD_F32 ? 4 : 2;
+    L.field = align_up(L.npad * L.elem);
+    L.f32field = align_up(L.npad * 4);
+    L.c_off = 0;
+    L.gz_off = L.c_off + L.f32field;
+    L.gy_off = L.gz_off + align_up((size_t)g.nz * 4);
+    L.gx_off = L.gy_off + align_up((size_t)g.ny * 4);
+    L.scratch_off = L.gx_off + align_up((size_t)g.nx * 4);
+    L.model_bytes = L.scratch_off + kAlign;
+    L.meta_off = 2 * L.field;
+    L.state_bytes = L.meta_off + kAlign;
+    return L;
+}
+
+size_t ckpt_slot_bytes(const Layout &L) { return 2 * L.field; }
+
+int64_t n_ckpt(int64_t nt, int32_t every) { return (nt + every - 1) / every; }
+
+size_t adjoint_work_bytes(const Layout &L, int32_t every)
+{
+    // recompute state (2) + L w history (every) + adjoint fields (2) + FP64 sum
+    return 2 * L.f32field + (size_t)every * L.f32field + 2 * L.f32field +
+           align_up(L.npad * 8);
+}
+
+fd_status check_grid(const fd_grid *g)
+{
+    if (!g) return fail(FD_ERR_INVALID_ARG, "grid is NULL");
+    if (g->ndim != 2 && g->ndim != 3) return fail(FD_ERR_INVALID_ARG, "ndim must be 2 or 3 (got %d)", g->ndim);
+    if (g->nz < 1 || g->ny < 1 || g->nx < 1 || g->nz > kMaxDim || g->ny > kMaxDim || g->nx > kMaxDim)
+        return fail(FD_ERR_INVALID_ARG, "grid sizes must be in [1, 2^30] (nz=%lld ny=%lld nx=%lld)",
+                    (long long)g->nz, (long long)g->ny, (long long)g->nx);
+    if (g->ndim == 2 && g->ny != 1) return fail(FD_ERR_INVALID_ARG, "2D grids need ny == 1");
+    if (!(g->dh > 0.0) || !std::isfinite(g->dh)) return fail(FD_ERR_INVALID_ARG, "dh must be > 0");
+    if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return fail(FD_ERR_INVALID_ARG, "dt must be > 0");
+    if (g->radius < 1) return fail(FD_ERR_INVALID_ARG, "radius must be >= 1");
+    if (g->radius != 4) return fail(FD_ERR_UNSUPPORTED, "only radius 4 (8th order) is built");
+    if (g->bc == FD_BC_PERIODIC) return fail(FD_ERR_UNSUPPORTED, "periodic edges are not built");
+    if (g->bc != FD_BC_ZERO) return fail(FD_ERR_INVALID_ARG, "unknown boundary kind %d", g->bc);
+    if (g->sponge_width < 0) return fail(FD_ERR_INVALID_ARG, "sponge_width must be >= 0");
+    if (g->sponge_faces & ~0x3Fu) return fail(FD_ERR_INVALID_ARG, "unknown sponge face bits");
+    if (!std::isfinite(g->sponge_alpha)) return fail(FD_ERR_INVALID_ARG, "sponge_alpha must be finite");
+    if (g->storage != FD_F32 && g->storage != FD_F16 && g->storage != FD_BF16)
+        return fail(FD_ERR_INVALID_ARG, "unknown storage kind %d", g->storage);
+    const double cells = (double)g->nz * (double)g->ny * (double)((g->nx + 63) / 64 * 64);
+    if (cells > 4.0e9) return fail(FD_ERR_INVALID_ARG, "grid too large");
+    return FD_OK;
+}
+
+}  // namespace
+
+struct fd_model {
+    fd_grid grid;
+    Layout L;
+    float *c, *gz, *gy, *gx;
+    uint32_t *scratch;
+    float amp;  // dt^2 / h^D
+};
+
+struct fd_state {
+    const fd_model *m;
+    void *buf[2];
+    int32_t *meta;
+    int64_t next;  // next step index, -1 before fd_begin_shot
+};
+
+namespace {
+
+fd_status check_shot(const fd_model *m, const fd_shot *s)
+{
+    if (!s) return fail(FD_ERR_INVALID_ARG, "shot is NULL");
+    const Layout &L = m->L;
+    if (s->nt < 1) return fail(FD_ERR_INVALID_ARG, "shot nt must be >= 1");
+    if (!s->wavelet) return fail(FD_ERR_INVALID_ARG, "shot wavelet is NULL");
+    if (s->src_z < 0 || s->src_z >= L.nz || s->src_y < 0 || s->src_y >= L.ny || s->src_x < 0 ||
+        s->src_x >= L.nx)
+        return fail(FD_ERR_INVALID_ARG, "source cell (%lld, %lld, %lld) outside the grid",
+                    (long long)s->src_z, (long long)s->src_y, (long long)s->src_x);
+    const fd_receivers &r = s->rec;
+    const int64_t nrec = r.nz * r.ny * r.nx;
+    if (r.nz < 0 || r.ny < 0 || r.nx < 0) return fail(FD_ERR_INVALID_ARG, "negative receiver counts");
+    if (nrec == 0) {
+        if (r.nz || r.ny || r.nx) return fail(FD_ERR_INVALID_ARG, "receiver counts must be all zero or all positive");
+        return FD_OK;
+    }
+    if (nrec > ((int64_t)1 << 30)) return fail(FD_ERR_INVALID_ARG, "too many receivers");
+    if (r.dz < 1 || r.dy < 1 || r.dx < 1) return fail(FD_ERR_INVALID_ARG, "receiver strides must be >= 1");
+    if (r.z0 < 0 || r.y0 < 0 || r.x0 < 0 || r.z0 + (r.nz - 1) * r.dz >= L.nz ||
+        r.y0 + (r.ny - 1) * r.dy >= L.ny || r.x0 + (r.nx - 1) * r.dx >= L.nx)
+        return fail(FD_ERR_INVALID_ARG, "receiver array leaves the grid");
+    return FD_OK;
+}
+
+int64_t nrec_of(const fd_shot *s) { return s->rec.nz * s->rec.ny * s->rec.nx; }
+
+StepArgs base_args(const fd_model *m, const fd_shot *s)
+{
+    StepArgs a{};
+    const Layout &L = m->L;
+    a.c = m->c;
+    a.gz = m->gz;
+    a.gy = m->gy;
+    a.gx = m->gx;
+    a.nz = (int32_t)L.nz;
+    a.ny = (int32_t)L.ny;
+    a.nx = (int32_t)L.nx;
+    a.px = L.px;
+    a.amp = m->amp;
+    if (s) {
+        a.sz = (int32_t)s->src_z;
+        a.sy = (int32_t)s->src_y;
+        a.sx = (int32_t)s->src_x;
+        a.wavelet = s->wavelet;
+        a.nt = s->nt;
+        const fd_receivers &r = s->rec;
+        if (nrec_of(s) > 0) {
+            a.rec = fdk::RecBox{(int32_t)r.z0, (int32_t)r.y0, (int32_t)r.x0, (int32_t)r.nz,
+                                (int32_t)r.ny, (int32_t)r.nx, (int32_t)r.dz, (int32_t)r.dy,
+                                (int32_t)r.dx};
+        } else {
+            a.rec = fdk::RecBox{0, 0, 0, 0, 0, 0, 1, 1, 1};
+        }
+    }
+    return a;
+}
+
+size_t src_offset(const Layout &L, const fd_shot *s)
+{
+    return ((size_t)s->src_z * (size_t)L.ny + (size_t)s->src_y) * (size_t)L.px + (size_t)s->src_x;
+}
+
+fd_status do_begin(const fd_model *m, fd_state *st, const fd_shot *s, hipStream_t stream)
+{
+    const Layout &L = m->L;
+    hipError_t e = fdk::launch_fill_u32(st->buf[0], L.state_bytes / 4, 0u, stream);
+    if (e != hipSuccess) return hip_fail(e, "fd_begin_shot fill");
+    e = fdk::launch_begin(L.storage, st->buf[0], (int64_t)src_offset(L, s), m->amp, s->wavelet,
+                          st->meta, stream);
+    if (e != hipSuccess) return hip_fail(e, "fd_begin_shot");
+    st->next = 0;
+    return FD_OK;
+}
+
+fd_status do_step(const fd_model *m, fd_state *st, const fd_shot *s, int64_t n, float *trace_row,
+                  hipStream_t stream)
+{
+    StepArgs a = base_args(m, s);
+    a.cur = st->buf[n & 1];
+    a.prev = st->buf[(n + 1) & 1];
+    a.n = n;
+    a.trace_row = nrec_of(s) > 0 ? trace_row : nullptr;
+    a.meta = st->meta;
+    hipError_t e = fdk::launch_step(a, m->L.ndim, m->L.storage, fdk::kFwd, stream);
+    if (e != hipSuccess) return hip_fail(e, "step kernel launch");
+    st->next = n + 1;
+    return FD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *fd_last_error(void) { return g_err.c_str(); }
+
+const char *fd_version(void) { return "fd-mi355x 0.1 (gfx950, radius 4)"; }
+
+fd_status fd_query_bytes(const fd_grid *grid, int64_t nt, int32_t ckpt_every, fd_sizes *out)
+{
+    fd_status st = check_grid(grid);
+    if (st != FD_OK) return st;
+    if (!out) return fail(FD_ERR_INVALID_ARG, "out is NULL");
+    if (nt < 0 || ckpt_every < 0) return fail(FD_ERR_INVALID_ARG, "nt and ckpt_every must be >= 0");
+    const Layout L = make_layout(*grid);
+    out->model = L.model_bytes;
+    out->state = L.state_bytes;
+    out->checkpoints = (nt > 0 && ckpt_every > 0) ? (size_t)n_ckpt(nt, ckpt_every) * ckpt_slot_bytes(L) : 0;
+    out->adjoint_work = ckpt_every > 0 ? adjoint_work_bytes(L, ckpt_every) : 0;
+    return ok();
+}
+
+fd_status fd_create_model(const fd_grid *grid, const float *velocity, void *model_buf,
+                          size_t model_bytes, void *stream, fd_model **out)
+{
+    fd_status st = check_grid(grid);
+    if (st != FD_OK) return st;
+    if (!velocity || !model_buf || !out) return fail(FD_ERR_INVALID_ARG, "NULL velocity, buffer or out");
+    const Layout L = make_layout(*grid);
+    if (model_bytes < L.model_bytes)
+        return fail(FD_ERR_INVALID_ARG, "model buffer too small (%zu < %zu bytes)", model_bytes, L.model_bytes);
+    if ((uintptr_t)model_buf % kAlign) return fail(FD_ERR_INVALID_ARG, "model buffer must be 256-byte aligned");
+
+    fd_model *m = new (std::nothrow) fd_model;
+    if (!m) return fail(FD_ERR_OUT_OF_MEMORY, "host allocation failed");
+    m->grid = *grid;
+    if (m->grid.sponge_width > 0 && !(m->grid.sponge_alpha > 0.0))
+        m->grid.sponge_alpha = 0.3 / m->grid.sponge_width;
+    m->L = L;
+    char *base = (char *)model_buf;
+    m->c = (float *)(base + L.c_off);
+    m->gz = (float *)(base + L.gz_off);
+    m->gy = (float *)(base + L.gy_off);
+    m->gx = (float *)(base + L.gx_off);
+    m->scratch = (uint32_t *)(base + L.scratch_off);
+    m->amp = (float)(grid->dt * grid->dt / std::pow(grid->dh, (double)grid->ndim));
+
+    // Damping profiles g(i) = exp(-(alpha d)^2), FP64 on the host, stored FP32.
+    const double alpha = m->grid.sponge_alpha;
+    const int32_t W = m->grid.sponge_width;
+    const uint32_t f = m->grid.sponge_faces;
+    auto profile = [&](int64_t n, bool lo, bool hi) {
+        std::vector<float> g((size_t)n);
+        for (int64_t i = 0; i < n; ++i) {
+            double d = 0.0;
+            if (W > 0) {
+                if (lo && (double)(W - i) > d) d = (double)(W - i);
+                if (hi && (double)(i - (n - 1 - W)) > d) d = (double)(i - (n - 1 - W));
+            }
+            g[(size_t)i] = (float)std::exp(-(alpha * d) * (alpha * d));
+        }
+        return g;
+    };
+    const std::vector<float> gz = profile(L.nz, f & FD_FACE_ZLO, f & FD_FACE_ZHI);
+    const std::vector<float> gy = grid->ndim == 3 ? profile(L.ny, f & FD_FACE_YLO, f & FD_FACE_YHI)
+                                                  : std::vector<float>(1, 1.0f);
+    const std::vector<float> gx = profile(L.nx, f & FD_FACE_XLO, f & FD_FACE_XHI);
+
+    hipStream_t s = (hipStream_t)stream;
+    uint32_t host_scratch[2] = {0, 0};
+    hipError_t e = hipMemcpyAsync(m->gz, gz.data(), gz.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(m->gy, gy.data(), gy.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(m->gx, gx.data(), gx.size() * 4, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = fdk::launch_fill_u32(m->c, L.npad, 0u, s);
+    if (e == hipSuccess) e = fdk::launch_fill_u32(m->scratch, 2, 0u, s);
+    if (e == hipSuccess)
+        e = fdk::launch_model_c(velocity, m->c, L.nz * L.ny, (int32_t)L.nx, L.px,
+                                grid->dt / grid->dh, m->scratch, s);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_scratch, m->scratch, 8, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        delete m;
+        return hip_fail(e, "fd_create_model");
+    }
+    if (host_scratch[1]) {
+        delete m;
+        return fail(FD_ERR_INVALID_ARG, "velocity must be positive and finite everywhere");
+    }
+    float vmax;
+    std::memcpy(&vmax, &host_scratch[0], 4);
+    const double cfl = (double)vmax * grid->dt / grid->dh;
+    const double lhs = cfl * cfl * grid->ndim * kSymbolMax;
+    if (!(lhs <= 4.0)) {
+        delete m;
+        return fail(FD_ERR_UNSTABLE,
+                    "unstable: vmax*dt/dh = %.6f exceeds the %dD limit %.6f", cfl, grid->ndim,
+                    std::sqrt(4.0 / (grid->ndim * kSymbolMax)));
+    }
+    *out = m;
+    return ok();
+}
+
+fd_status fd_destroy_model(fd_model *model)
+{
+    delete model;
+    return ok();
+}
+
+fd_status fd_create_state(const fd_model *model, void *state_buf, size_t state_bytes, fd_state **out)
+{
+    if (!model || !state_buf || !out) return fail(FD_ERR_INVALID_ARG, "NULL model, buffer or out");
+    if (state_bytes < model->L.state_bytes)
+        return fail(FD_ERR_INVALID_ARG, "state buffer too small (%zu < %zu bytes)", state_bytes,
+                    model->L.state_bytes);
+    if ((uintptr_t)state_buf % kAlign) return fail(FD_ERR_INVALID_ARG, "state buffer must be 256-byte aligned");
+    fd_state *st = new (std::nothrow) fd_state;
+    if (!st) return fail(FD_ERR_OUT_OF_MEMORY, "host allocation failed");
+    st->m = model;
+    st->buf[0] = state_buf;
+    st->buf[1] = (char *)state_buf + model->L.field;
+    st->meta = (int32_t *)((char *)state_buf + model->L.meta_off);
+    st->next = -1;
+    *out = st;
+    return ok();
+}
+
+fd_status fd_destroy_state(fd_state *state)
+{
+    delete state;
+    return ok();
+}
+
+fd_status fd_begin_shot(const fd_model *model, fd_state *state, const fd_shot *shot, void *stream)
+{
+    if (!model || !state) return fail(FD_ERR_INVALID_ARG, "NULL model or state");
+    if (state->m != model) return fail(FD_ERR_INVALID_ARG, "state was created for another model");
+    fd_status st = check_shot(model, shot);
+    if (st != FD_OK) return st;
+    st = do_begin(model, state, shot, (hipStream_t)stream);
+    return st == FD_OK ? ok() : st;
+}
+
+fd_status fd_step(const fd_model *model, fd_state *state, const fd_shot *shot, int64_t n,
+                  float *trace_row, void *stream)
+{
+    if (!model || !state) return fail(FD_ERR_INVALID_ARG, "NULL model or state");
+    if (state->m != model) return fail(FD_ERR_INVALID_ARG, "state was created for another model");
+    fd_status st = check_shot(model, shot);
+    if (st != FD_OK) return st;
+    if (state->next < 0) return fail(FD_ERR_INVALID_ARG, "fd_begin_shot has not been called");
+    if (n != state->next) return fail(FD_ERR_INVALID_ARG, "step %lld requested, next step is %lld",
+                                      (long long)n, (long long)state->next);
+    if (n >= shot->nt) return fail(FD_ERR_INVALID_ARG, "step %lld beyond the shot's %lld steps",
+                                   (long long)n, (long long)shot->nt);
+    st = do_step(model, state, shot, n, trace_row, (hipStream_t)stream);
+    return st == FD_OK ? ok() : st;
+}
+
+fd_status fd_run_shot(const fd_model *model, fd_state *state, const fd_shot *shot, float *traces,
+                      void *ckpt, size_t ckpt_bytes, int32_t ckpt_every, void *stream)
+{
+    if (!model || !state) return fail(FD_ERR_INVALID_ARG, "NULL model or state");
+    if (state->m != model) return fail(FD_ERR_INVALID_ARG, "state was created for another model");
+    fd_status st = check_shot(model, shot);
+    if (st != FD_OK) return st;
+    const Layout &L = model->L;
+    if (ckpt) {
+        if (ckpt_every < 1) return fail(FD_ERR_INVALID_ARG, "ckpt_every must be >= 1");
+        const size_t need = (size_t)n_ckpt(shot->nt, ckpt_every) * ckpt_slot_bytes(L);
+        if (ckpt_bytes < need)
+            return fail(FD_ERR_INVALID_ARG, "checkpoint buffer too small (%zu < %zu bytes)", ckpt_bytes, need);
+        if ((uintptr_t)ckpt % kAlign) return fail(FD_ERR_INVALID_ARG, "checkpoint buffer must be 256-byte aligned");
+    }
+    hipStream_t s = (hipStream_t)stream;
+    st = do_begin(model, state, shot, s);
+    if (st != FD_OK) return st;
+    const int64_t nrec = nrec_of(shot);
+    for (int64_t n = 0; n < shot->nt; ++n) {
+        if (ckpt && n % ckpt_every == 0) {
+            char *slot = (char *)ckpt + (size_t)(n / ckpt_every) * ckpt_slot_bytes(L);
+            hipError_t e = hipMemcpyAsync(slot, state->buf[n & 1], L.field, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess)
+                e = hipMemcpyAsync(slot + L.field, state->buf[(n + 1) & 1], L.field,
+                                   hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+        }
+        st = do_step(model, state, shot, n, traces ? traces + (size_t)n * (size_t)nrec : nullptr, s);
+        if (st != FD_OK) return st;
+    }
+    return ok();
+}
+
+fd_status fd_adjoint_gradient(const fd_model *model, const fd_shot *shot, const float *adj,
+                              const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every, void *work,
+                              size_t work_bytes, double *grad_v, void *stream)
+{
+    if (!model) return fail(FD_ERR_INVALID_ARG, "NULL model");
+    fd_status st = check_shot(model, shot);
+    if (st != FD_OK) return st;
+    const Layout &L = model->L;
+    if (L.storage != FD_F32) return fail(FD_ERR_UNSUPPORTED, "the adjoint needs FP32 storage");
+    if (!adj || !ckpt || !work || !grad_v) return fail(FD_ERR_INVALID_ARG, "NULL adj, ckpt, work or grad_v");
+    if (ckpt_every < 1) return fail(FD_ERR_INVALID_ARG, "ckpt_every must be >= 1");
+    const int64_t nt = shot->nt;
+    const int64_t nseg = n_ckpt(nt, ckpt_every);
+    if (ckpt_bytes < (size_t)nseg * ckpt_slot_bytes(L))
+        return fail(FD_ERR_INVALID_ARG, "checkpoint buffer too small");
+    if (work_bytes < adjoint_work_bytes(L, ckpt_every))
+        return fail(FD_ERR_INVALID_ARG, "adjoint work buffer too small (%zu < %zu bytes)", work_bytes,
+                    adjoint_work_bytes(L, ckpt_every));
+    if ((uintptr_t)work % kAlign) return fail(FD_ERR_INVALID_ARG, "work buffer must be 256-byte aligned");
+    hipStream_t s = (hipStream_t)stream;
+    char *w = (char *)work;
+    void *fw[2] = {w, w + L.f32field};
+    float *lap = (float *)(w + 2 * L.f32field);
+    char *zb = w + 2 * L.f32field + (size_t)ckpt_every * L.f32field;
+    void *zf[2] = {zb, zb + L.f32field};
+    double *g = (double *)(zb + 2 * L.f32field);
+    const int64_t nrec = nrec_of(shot);
+
+    hipError_t e = fdk::launch_fill_u32(zf[0], (2 * L.f32field + align_up(L.npad * 8)) / 4, 0u, s);
+    if (e != hipSuccess) return hip_fail(e, "adjoint clear");
+    for (int64_t seg = nseg - 1; seg >= 0; --seg) {
+        const int64_t n0 = seg * ckpt_every;
+        const int64_t n1 = std::min<int64_t>(nt, n0 + ckpt_every);
+        const char *slot = (const char *)ckpt + (size_t)seg * ckpt_slot_bytes(L);
+        e = hipMemcpyAsync(fw[n0 & 1], slot, L.field, hipMemcpyDeviceToDevice, s);
+        if (e == hipSuccess)
+            e = hipMemcpyAsync(fw[(n0 + 1) & 1], slot + L.field, L.field, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "checkpoint restore");
+        for (int64_t n = n0; n < n1; ++n) {
+            StepArgs a = base_args(model, shot);
+            a.cur = fw[n & 1];
+            a.prev = fw[(n + 1) & 1];
+            a.n = n;
+            a.trace_row = nullptr;
+            a.lap = (float *)((char *)lap + (size_t)(n - n0) * L.f32field);
+            e = fdk::launch_step(a, L.ndim, L.storage, fdk::kFwdLap, s);
+            if (e != hipSuccess) return hip_fail(e, "recompute step");
+        }
+        for (int64_t k = n1; k >= n0 + 1; --k) {
+            StepArgs a = base_args(model, shot);
+            a.cur = zf[(k + 1) & 1];
+            a.prev = zf[k & 1];
+            a.n = k;
+            a.nt = 0;  // no source in the adjoint recursion
+            a.lap = (float *)((char *)lap + (size_t)(k - 1 - n0) * L.f32field);
+            a.resid_row = nrec > 0 ? adj + (size_t)(k - 1) * (size_t)nrec : nullptr;
+            a.g = g;
+            e = fdk::launch_step(a, L.ndim, L.storage, fdk::kAdj, s);
+            if (e != hipSuccess) return hip_fail(e, "adjoint step");
+        }
+    }
+    e = fdk::launch_grad_finish(g, model->c, grad_v, L.nz * L.ny, (int32_t)L.nx, L.px,
+                                2.0 * model->grid.dt / model->grid.dh, s);
+    if (e != hipSuccess) return hip_fail(e, "gradient finish");
+    return ok();
+}
+
+fd_status fd_get_wavefield(const fd_state *state, int32_t which, float *out, void *stream)
+{
+    if (!state || !out) return fail(FD_ERR_INVALID_ARG, "NULL state or out");
+    if (which != 0 && which != 1) return fail(FD_ERR_INVALID_ARG, "which must be 0 (P) or 1 (Pold)");
+    if (state->next < 0) return fail(FD_ERR_INVALID_ARG, "fd_begin_shot has not been called");
+    const Layout &L = state->m->L;
+    const int64_t lvl = which == 0 ? state->next : state->next - 1;
+    const void *buf = state->buf[lvl & 1];
+    hipError_t e = fdk::launch_get_field(L.storage, buf, out, L.nz * L.ny, (int32_t)L.nx, L.px,
+                                         state->meta, (int32_t)(lvl & 3), (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fd_get_wavefield");
+    return ok();
+}
+
+fd_status fd_set_wavefield(fd_state *state, int32_t which, const float *in, void *stream)
+{
+    if (!state || !in) return fail(FD_ERR_INVALID_ARG, "NULL state or in");
+    if (which != 0 && which != 1) return fail(FD_ERR_INVALID_ARG, "which must be 0 (P) or 1 (Pold)");
+    const Layout &L = state->m->L;
+    hipStream_t s = (hipStream_t)stream;
+    if (state->next < 0) {
+        hipError_t e = fdk::launch_fill_u32(state->buf[0], L.state_bytes / 4, 0u, s);
+        if (e != hipSuccess) return hip_fail(e, "fd_set_wavefield clear");
+        state->next = 0;
+    }
+    const int64_t lvl = which == 0 ? state->next : state->next - 1;
+    hipError_t e = fdk::launch_set_field(L.storage, in, state->buf[lvl & 1], L.nz * L.ny,
+                                         (int32_t)L.nx, L.px, state->meta, (int32_t)(lvl & 3), s);
+    if (e != hipSuccess) return hip_fail(e, "fd_set_wavefield");
+    return ok();
+}
+
+fd_status fd_step_batch(fd_batch_item *items, int32_t count, int32_t nsteps, void *stream)
+{
+    if (count < 0 || count > FD_BATCH_MAX) return fail(FD_ERR_INVALID_ARG, "count must be in [0, %d]", FD_BATCH_MAX);
+    if (count > 0 && !items) return fail(FD_ERR_INVALID_ARG, "items is NULL");
+    if (nsteps < 0) return fail(FD_ERR_INVALID_ARG, "nsteps must be >= 0");
+    for (int32_t i = 0; i < count; ++i) {
+        const fd_batch_item &it = items[i];
+        if (!it.model || !it.state) return fail(FD_ERR_INVALID_ARG, "item %d: NULL model or state", i);
+        if (it.state->m != it.model) return fail(FD_ERR_INVALID_ARG, "item %d: state of another model", i);
+        if (it.model->L.ndim != 2 || it.model->L.storage != FD_F32)
+            return fail(FD_ERR_UNSUPPORTED, "item %d: batching is built for 2D FP32 grids", i);
+        fd_status st = check_shot(it.model, it.shot);
+        if (st != FD_OK) return st;
+        if (it.state->next < 0) return fail(FD_ERR_INVALID_ARG, "item %d: fd_begin_shot has not been called", i);
+        if (it.n != it.state->next) return fail(FD_ERR_INVALID_ARG, "item %d: n is not the state's next step", i);
+        for (int32_t j = 0; j < i; ++j)
+            if (items[j].state == it.state) return fail(FD_ERR_INVALID_ARG, "item %d repeats a state", i);
+    }
+    hipStream_t s = (hipStream_t)stream;
+    for (int32_t step = 0; step < nsteps; ++step) {
+        fdk::Batch2D b;
+        b.count = 0;
+        int32_t which[FD_BATCH_MAX];
+        for (int32_t i = 0; i < count; ++i) {
+            fd_batch_item &it = items[i];
+            if (it.n >= it.shot->nt) continue;
+            StepArgs a = base_args(it.model, it.shot);
+            a.cur = it.state->buf[it.n & 1];
+            a.prev = it.state->buf[(it.n + 1) & 1];
+            a.n = it.n;
+            a.trace_row = (it.traces && nrec_of(it.shot) > 0)
+                              ? it.traces + (size_t)it.n * (size_t)nrec_of(it.shot) : nullptr;
+            a.meta = it.state->meta;
+            b.it[b.count] = a;
+            which[b.count] = i;
+            ++b.count;
+        }
+        if (b.count == 0) break;
+        hipError_t e = fdk::launch_step_batch2d(b, s);
+        if (e != hipSuccess) return hip_fail(e, "batched step launch");
+        for (int32_t k = 0; k < b.count; ++k) {
+            fd_batch_item &it = items[which[k]];
+            it.n += 1;
+            it.state->next = it.n;
+        }
+    }
+    return ok();
+}
+
+}  // extern "C"

@@ -1,0 +1,179 @@
+// Device-side definitions shared by the step kernels (gfx950).
+//
+// One fused kernel computes one time step of the explicit scheme for the
+// acoustic wave equation (arXiv 2311.05038, Section 7, Eq. 1), i.e. the
+// routines of Listing 3 (source addition, z- and x-derivatives [and y],
+// time update, level rotation) in a single pass over HBM:
+//   new = G (2 cur + c L cur) - G^2 prev      (written over prev)
+// with receivers sampled from `new` and the next source addition applied to
+// `new` in the same pass.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace fdk {
+
+// 8th-order central second-difference weights (radius 4), h = 1.
+constexpr float kA0 = (float)(-205.0 / 72.0);
+constexpr float kA1 = (float)(8.0 / 5.0);
+constexpr float kA2 = (float)(-1.0 / 5.0);
+constexpr float kA3 = (float)(8.0 / 315.0);
+constexpr float kA4 = (float)(-1.0 / 560.0);
+
+enum Mode : int {
+    kFwd = 0,     // forward step
+    kFwdLap = 1,  // forward step that also stores L(cur) (adjoint recompute)
+    kAdj = 2      // adjoint step: receiver injection of c G r, g += new * L(w)
+};
+
+enum StorageKind : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
+
+struct RecBox {
+    int32_t z0, y0, x0;
+    int32_t nz, ny, nx;
+    int32_t dz, dy, dx;
+};
+
+// Arguments of one step on one grid.  Field buffers use a padded layout:
+// element (z, y, x) sits at (z * ny + y) * px + x with px a multiple of 64;
+// cells with x >= nx are zero in every field.
+struct StepArgs {
+    const void *cur;      // level n
+    void *prev;           // level n-1 in, level n+1 out
+    const float *c;       // (v dt / h)^2, padded, zero in padding
+    const float *gz, *gy, *gx;  // damping profiles (nz, ny, nx entries)
+    int32_t nz, ny, nx, px;
+    int32_t zc;           // planes (rows in 2D) per block
+    int32_t tiles_x, tiles_y, tiles_z;
+    int32_t sz, sy, sx;   // source cell
+    float amp;            // dt^2 / h^D
+    const float *wavelet; // device, nt samples
+    int64_t n, nt;
+    RecBox rec;
+    float *trace_row;     // nrec floats of row n, or null
+    int32_t *meta;        // 16-bit storage: e[4] exponents then max|.|[4] bits
+    float *lap;           // kFwdLap: out;  kAdj: in (L w^{k-1}), padded FP32
+    const float *resid_row;  // kAdj: dJ/dtraces row k-1 (nrec), or null
+    double *g;            // kAdj: FP64 accumulator, padded
+};
+
+template <int ST> struct Stor { using T = uint16_t; };
+template <> struct Stor<kF32> { using T = float; };
+
+template <typename T, int VX>
+struct alignas(sizeof(T) * VX) Pack {
+    T v[VX];
+};
+
+template <typename T, int VX>
+__device__ __forceinline__ Pack<T, VX> ldp(const T *p)
+{
+    return *reinterpret_cast<const Pack<T, VX> *>(p);
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void stp(T *p, const Pack<T, VX> &x)
+{
+    *reinterpret_cast<Pack<T, VX> *>(p) = x;
+}
+
+template <int ST>
+__device__ __forceinline__ float decode(typename Stor<ST>::T q, float scale)
+{
+    if constexpr (ST == kF32) {
+        return q;
+    } else if constexpr (ST == kF16) {
+        return (float)__builtin_bit_cast(_Float16, q) * scale;
+    } else {
+        return __uint_as_float((uint32_t)q << 16) * scale;
+    }
+}
+
+// Round-to-nearest-even encode of x * inv_scale.
+template <int ST>
+__device__ __forceinline__ typename Stor<ST>::T encode(float x, float inv_scale)
+{
+    if constexpr (ST == kF32) {
+        return x;
+    } else if constexpr (ST == kF16) {
+        return __builtin_bit_cast(uint16_t, (_Float16)(x * inv_scale));
+    } else {
+        uint32_t u = __float_as_uint(x * inv_scale);
+        u += 0x7FFFu + ((u >> 16) & 1u);
+        return (uint16_t)(u >> 16);
+    }
+}
+
+// 2^e for e in [-126, 127].
+__device__ __forceinline__ float pow2i(int e) { return __uint_as_float((uint32_t)(e + 127) << 23); }
+
+// floor(log2(max(m, 2^-100))) - 11: the storage exponent of a field whose
+// magnitude is bounded by 7 m (16x headroom below binary16's largest value).
+__device__ __forceinline__ int storage_exponent(float m)
+{
+    const float floor_m = 7.888609052210118e-31f;  // 2^-100
+    float t = m > floor_m ? m : floor_m;
+    return (int)((__float_as_uint(t) >> 23) & 0xFFu) - 127 - 11;
+}
+
+// Per-launch quantities of the 16-bit storage form.
+struct HalfCtx {
+    float sc, sp, sn_inv;  // decode scale of cur and prev, encode scale of new
+};
+
+template <int ST>
+__device__ __forceinline__ HalfCtx half_prologue(const StepArgs &a, float inj, bool leader)
+{
+    HalfCtx h{1.0f, 1.0f, 1.0f};
+    if constexpr (ST != kF32) {
+        const int ic = (int)(a.n & 3), ip = (int)((a.n + 3) & 3);
+        const int in = (int)((a.n + 1) & 3), iz = (int)((a.n + 2) & 3);
+        const int ec = a.meta[ic], ep = a.meta[ip];
+        float m = fmaxf(__uint_as_float((uint32_t)a.meta[4 + ic]),
+                        __uint_as_float((uint32_t)a.meta[4 + ip]));
+        m = fmaxf(m, fabsf(inj));
+        const int en = storage_exponent(m);
+        h.sc = pow2i(ec);
+        h.sp = pow2i(ep);
+        h.sn_inv = pow2i(-en);
+        if (leader) {
+            a.meta[in] = en;
+            a.meta[4 + iz] = 0;  // slot of level n+2, filled by the next step
+        }
+    }
+    return h;
+}
+
+// Block-wide max of non-negative floats, folded into meta by atomicMax on
+// the bit pattern (order-independent, hence deterministic).
+template <int NT>
+__device__ __forceinline__ void block_max_to(int32_t *slot, float v, float *red)
+{
+    for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
+    if constexpr (NT == 64) {
+        if (threadIdx.x == 0) atomicMax((unsigned int *)slot, __float_as_uint(v));
+    } else {
+        const int w = threadIdx.x >> 6;
+        __syncthreads();
+        if ((threadIdx.x & 63) == 0) red[w] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            float m = red[0];
+            for (int i = 1; i < NT / 64; ++i) m = fmaxf(m, red[i]);
+            atomicMax((unsigned int *)slot, __float_as_uint(m));
+        }
+    }
+}
+
+// Maps the hardware block index to a logical tile so that each XCD (blocks
+// are dealt round-robin to the 8 XCDs) works on one contiguous range of
+// tiles, which keeps neighbouring tiles' halo reads in the same L2.
+__device__ __forceinline__ int xcd_tile(int bid, int nblocks)
+{
+    const int per = nblocks >> 3;
+    if (bid < (per << 3)) return (bid & 7) * per + (bid >> 3);
+    return bid;
+}
+
+}  // namespace fdk

@@ -1,0 +1,745 @@
+// Step kernels and set-up kernels for gfx950 (MI355X).
+//
+// 2D (z, x):  one wave per block.  A block owns a 64*VX-wide column strip and
+//   a chunk of `zc` rows; each lane streams its VX columns down z keeping the
+//   9 rows z-4..z+4 in registers, and the x-neighbours come from one LDS row
+//   (plus 4 halo cells each side).  One HBM read of cur/prev/c and one write
+//   per cell and step (16 B/cell in FP32, 10 B with 16-bit fields).
+// 3D (z, y, x): 4 waves per block.  A block owns a (64*VX) x (4*RY) tile of
+//   the x-y plane and a chunk of `zc` planes; lanes stream along z (the slow
+//   axis) with a 9-deep register queue per cell, and x/y neighbours come from
+//   a double-buffered LDS copy of the current plane with a 4-cell halo.
+// Both follow the fused step of arXiv 2311.05038, Section 7 (Listing 3's
+// add_source, fd_pzz, fd_pxx, fd_time and swap in one pass).
+#include "fd_device.hpp"
+#include "fd_launch.hpp"
+
+namespace fdk {
+
+// --------------------------------------------------------------------------
+// Epilogue shared by 2D and 3D: receivers, source, padding, store.
+// --------------------------------------------------------------------------
+template <int ST, int VX, int MODE>
+__device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h, int z, int y,
+                                             int x0, bool store_ok, size_t off, float (&nw)[VX],
+                                             const float (&lp)[VX], const float (&cc)[VX],
+                                             const float (&G)[VX], float inj, float &bmax)
+{
+    using T = typename Stor<ST>::T;
+    // Receiver box membership of this row (z, y).
+    int rrow = -1;
+    {
+        const int zr = z - a.rec.z0, yr = y - a.rec.y0;
+        if (zr >= 0 && yr >= 0 && zr % a.rec.dz == 0 && yr % a.rec.dy == 0 &&
+            zr / a.rec.dz < a.rec.nz && yr / a.rec.dy < a.rec.ny)
+            rrow = (zr / a.rec.dz) * a.rec.ny + yr / a.rec.dy;
+    }
+    if constexpr (MODE == kAdj) {
+        if (a.resid_row != nullptr && rrow >= 0) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const int xr = x0 + v - a.rec.x0;
+                if (x0 + v < a.nx && xr >= 0 && xr % a.rec.dx == 0 && xr / a.rec.dx < a.rec.nx)
+                    nw[v] = fmaf(cc[v] * G[v], a.resid_row[(size_t)rrow * a.rec.nx + xr / a.rec.dx], nw[v]);
+            }
+        }
+    } else {
+        if (a.trace_row != nullptr && rrow >= 0) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const int xr = x0 + v - a.rec.x0;
+                if (x0 + v < a.nx && xr >= 0 && xr % a.rec.dx == 0 && xr / a.rec.dx < a.rec.nx)
+                    a.trace_row[(size_t)rrow * a.rec.nx + xr / a.rec.dx] = nw[v];
+            }
+        }
+        if (z == a.sz && y == a.sy) {
+#pragma unroll
+            for (int v = 0; v < VX; ++v)
+                if (x0 + v == a.sx) nw[v] += inj;
+        }
+    }
+#pragma unroll
+    for (int v = 0; v < VX; ++v) {
+        if (x0 + v >= a.nx) nw[v] = 0.0f;
+        if constexpr (ST != kF32) bmax = fmaxf(bmax, fabsf(nw[v]));
+    }
+    if (!store_ok) return;
+    T *prv = (T *)a.prev;
+    Pack<T, VX> o;
+#pragma unroll
+    for (int v = 0; v < VX; ++v) o.v[v] = encode<ST>(nw[v], h.sn_inv);
+    stp<T, VX>(prv + off, o);
+    if constexpr (MODE == kFwdLap) {
+        Pack<float, VX> L;
+#pragma unroll
+        for (int v = 0; v < VX; ++v) L.v[v] = (x0 + v < a.nx) ? lp[v] : 0.0f;
+        stp<float, VX>(a.lap + off, L);
+    }
+    if constexpr (MODE == kAdj) {
+        const Pack<float, VX> lw = ldp<float, VX>(a.lap + off);
+        Pack<double, VX> gg = ldp<double, VX>(a.g + off);
+#pragma unroll
+        for (int v = 0; v < VX; ++v) gg.v[v] = fma((double)nw[v], (double)lw.v[v], gg.v[v]);
+        stp<double, VX>(a.g + off, gg);
+    }
+}
+
+// sum_k a_k (u_{-k} + u_{+k}), k = 1..4.  The library is built with
+// -ffp-contract=off; every fused multiply-add is written out, so all kernel
+// variants round identically.
+__device__ __forceinline__ float stencil_taps(float m4, float m3, float m2, float m1, float p1,
+                                              float p2, float p3, float p4)
+{
+    return fmaf(kA4, m4 + p4, fmaf(kA3, m3 + p3, fmaf(kA2, m2 + p2, kA1 * (m1 + p1))));
+}
+
+// new = G (2 cur + c lap) - G^2 prev
+__device__ __forceinline__ float leapfrog(float G, float ctr, float c, float lap, float prev)
+{
+    return fmaf(G, fmaf(c, lap, 2.0f * ctr), -(G * G) * prev);
+}
+
+// --------------------------------------------------------------------------
+// 2D
+// --------------------------------------------------------------------------
+template <int ST, int VX, int MODE>
+__device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
+                                            float (*row)[64 * VX + 8], const HalfCtx &h,
+                                            float inj, float &bmax)
+{
+    using T = typename Stor<ST>::T;
+    constexpr int TX = 64 * VX;
+    const int lane = threadIdx.x & 63;
+    const int xb = tx * TX;
+    const int x0 = xb + lane * VX;
+    const int zb = tz * a.zc;
+    const int ze = min(zb + a.zc, a.nz);
+    const T *__restrict__ cur = (const T *)a.cur;
+    const T *__restrict__ prv = (const T *)a.prev;
+    const size_t px = (size_t)a.px;
+    const bool lane_in = x0 < a.px;
+    const int nx = a.nx, nz = a.nz;
+
+    float gxv[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) gxv[v] = (x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
+
+    int hx = -1, hslot = 0;
+    if (lane < 4) {
+        hx = xb - 4 + lane;
+        hslot = lane;
+    } else if (lane >= 60) {
+        hx = xb + TX + (lane - 60);
+        hslot = TX + 4 + (lane - 60);
+    }
+    const bool hlane = (lane < 4) || (lane >= 60);
+    const bool hvalid = hx >= 0 && hx < nx;
+
+    auto ld_cur = [&](int z, float (&o)[VX]) {
+        if (z >= 0 && z < nz && lane_in) {
+            const Pack<T, VX> p = ldp<T, VX>(cur + (size_t)z * px + x0);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = decode<ST>(p.v[v], h.sc);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
+        }
+    };
+    auto ld_prev = [&](int z, float (&o)[VX]) {
+        if (z < nz && lane_in) {
+            const Pack<T, VX> p = ldp<T, VX>(prv + (size_t)z * px + x0);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = decode<ST>(p.v[v], h.sp);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
+        }
+    };
+    auto ld_c = [&](int z, float (&o)[VX]) {
+        if (z < nz && lane_in) {
+            const Pack<float, VX> p = ldp<float, VX>(a.c + (size_t)z * px + x0);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = p.v[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
+        }
+    };
+    auto ld_halo = [&](int z) -> float {
+        return (hvalid && z < nz) ? decode<ST>(cur[(size_t)z * px + hx], h.sc) : 0.0f;
+    };
+
+    float q[9][VX];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) ld_cur(zb - 4 + k, q[k]);
+    float la[VX], pv[VX], cv[VX];
+    ld_cur(zb + 4, la);
+    ld_prev(zb, pv);
+    ld_c(zb, cv);
+    float hv = ld_halo(zb);
+
+    for (int z = zb; z < ze; ++z) {
+        float pc[VX], cc[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            q[8][v] = la[v];
+            pc[v] = pv[v];
+            cc[v] = cv[v];
+        }
+        const float hc = hv;
+        if (z + 1 < ze) {
+            ld_cur(z + 5, la);
+            ld_prev(z + 1, pv);
+            ld_c(z + 1, cv);
+            hv = ld_halo(z + 1);
+        }
+        float *rw = row[z & 1];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) rw[4 + lane * VX + v] = q[4][v];
+        if (hlane) rw[hslot] = hc;
+        __syncthreads();
+        const float gzz = a.gz[z];
+        float nw[VX], lp[VX], G[VX];
+#pragma unroll
+        for (int v = 0; v < VX; ++v) {
+            const int li = 4 + lane * VX + v;
+            const float lx = stencil_taps(rw[li - 4], rw[li - 3], rw[li - 2], rw[li - 1],
+                                          rw[li + 1], rw[li + 2], rw[li + 3], rw[li + 4]);
+            const float lz = stencil_taps(q[0][v], q[1][v], q[2][v], q[3][v], q[5][v], q[6][v],
+                                          q[7][v], q[8][v]);
+            const float lap = fmaf(2.0f * kA0, q[4][v], lz + lx);
+            G[v] = gzz * gxv[v];
+            nw[v] = leapfrog(G[v], q[4][v], cc[v], lap, pc[v]);
+            lp[v] = lap;
+        }
+        finish_cells<ST, VX, MODE>(a, h, z, 0, x0, lane_in, (size_t)z * px + x0, nw, lp, cc, G,
+                                   inj, bmax);
+#pragma unroll
+        for (int k = 0; k < 8; ++k)
+#pragma unroll
+            for (int v = 0; v < VX; ++v) q[k][v] = q[k + 1][v];
+    }
+}
+
+template <int ST, int VX, int MODE>
+__global__ __launch_bounds__(64) void k_step2d(StepArgs a)
+{
+    __shared__ float row[2][64 * VX + 8];
+    const int nb = a.tiles_x * a.tiles_z;
+    const int t = xcd_tile(blockIdx.x, nb);
+    const int tx = t % a.tiles_x, tz = t / a.tiles_x;
+    float inj = 0.0f;
+    if constexpr (MODE != kAdj)
+        if (a.n + 1 < a.nt) inj = a.amp * a.wavelet[a.n + 1];
+    const HalfCtx h = half_prologue<ST>(a, inj, blockIdx.x == 0 && threadIdx.x == 0);
+    float bmax = 0.0f;
+    step2d_tile<ST, VX, MODE>(a, tx, tz, row, h, inj, bmax);
+    if constexpr (ST != kF32) block_max_to<64>(&a.meta[4 + (int)((a.n + 1) & 3)], bmax, nullptr);
+}
+
+// Batched 2D FP32 forward step: block b belongs to the item whose tile range
+// holds b; every item keeps its own grid, fields and step index.
+template <int VX>
+__global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
+{
+    __shared__ float row[2][64 * VX + 8];
+    const int t = blockIdx.x;
+    int i = 0;
+    while (i + 1 < b.count && t >= b.begin[i + 1]) ++i;
+    const StepArgs &a = b.it[i];
+    const int lt = t - b.begin[i];
+    const int tx = lt % a.tiles_x, tz = lt / a.tiles_x;
+    const float inj = (a.n + 1 < a.nt) ? a.amp * a.wavelet[a.n + 1] : 0.0f;
+    const HalfCtx h{1.0f, 1.0f, 1.0f};
+    float bmax = 0.0f;
+    step2d_tile<kF32, VX, kFwd>(a, tx, tz, row, h, inj, bmax);
+}
+
+// --------------------------------------------------------------------------
+// 3D
+// --------------------------------------------------------------------------
+template <int ST, int VX, int RY, int MODE>
+__global__ __launch_bounds__(256) void k_step3d(StepArgs a)
+{
+    using T = typename Stor<ST>::T;
+    constexpr int TX = 64 * VX, TY = 4 * RY, LW = TX + 8, LH = TY + 8;
+    __shared__ float pl[2][LH * LW];
+    __shared__ float red[4];
+    const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+    const int nb = a.tiles_x * a.tiles_y * a.tiles_z;
+    const int t = xcd_tile(blockIdx.x, nb);
+    const int tx = t % a.tiles_x;
+    const int t2 = t / a.tiles_x;
+    const int ty = t2 % a.tiles_y, tz = t2 / a.tiles_y;
+    const int xb = tx * TX, yb = ty * TY, x0 = xb + lane * VX;
+    const int zb = tz * a.zc, ze = min(zb + a.zc, a.nz);
+    const int nx = a.nx, ny = a.ny, nz = a.nz;
+    const size_t px = (size_t)a.px, pp = (size_t)ny * px;
+    const bool lane_in = x0 < a.px;
+    const T *__restrict__ cur = (const T *)a.cur;
+    const T *__restrict__ prv = (const T *)a.prev;
+
+    float inj = 0.0f;
+    if constexpr (MODE != kAdj)
+        if (a.n + 1 < a.nt) inj = a.amp * a.wavelet[a.n + 1];
+    const HalfCtx h = half_prologue<ST>(a, inj, blockIdx.x == 0 && threadIdx.x == 0);
+
+    int yj[RY];
+    bool yin[RY];
+    float gyv[RY];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        yj[j] = yb + wy + 4 * j;
+        yin[j] = yj[j] < ny;
+        gyv[j] = yin[j] ? a.gy[yj[j]] : 0.0f;
+    }
+    float gxv[VX];
+#pragma unroll
+    for (int v = 0; v < VX; ++v) gxv[v] = (x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
+
+    // y-halo rows handled by this thread: k = wy + 4 hh, hh = 0, 1.
+    int hy[2], hyslot[2];
+    bool hyv[2];
+#pragma unroll
+    for (int hh = 0; hh < 2; ++hh) {
+        const int k = wy + 4 * hh;
+        const int ly = k < 4 ? k - 4 : TY + k - 4;
+        hy[hh] = yb + ly;
+        hyv[hh] = hy[hh] >= 0 && hy[hh] < ny && lane_in;
+        hyslot[hh] = (ly + 4) * LW + 4 + lane * VX;
+    }
+    // x-halo cell handled by this thread (threads < 8 TY).
+    const bool hxl = threadIdx.x < 8 * TY;
+    int hxx = 0, hxy = 0, hxslot = 0;
+    if (hxl) {
+        const int lr = threadIdx.x >> 3, ci = threadIdx.x & 7;
+        hxx = ci < 4 ? xb - 4 + ci : xb + TX + ci - 4;
+        hxy = yb + lr;
+        hxslot = (lr + 4) * LW + (ci < 4 ? ci : TX + ci);
+    }
+    const bool hxv = hxl && hxx >= 0 && hxx < nx && hxy < ny;
+
+    auto ld3 = [&](const T *base, int z, int y, float s, float (&o)[VX]) {
+        if (z >= 0 && z < nz && y < ny && lane_in) {
+            const Pack<T, VX> p = ldp<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = decode<ST>(p.v[v], s);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
+        }
+    };
+    auto ldc3 = [&](int z, int y, float (&o)[VX]) {
+        if (z < nz && y < ny && lane_in) {
+            const Pack<float, VX> p = ldp<float, VX>(a.c + (size_t)z * pp + (size_t)y * px + x0);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = p.v[v];
+        } else {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
+        }
+    };
+    auto ldhy = [&](int z, int hh, float (&o)[VX]) {
+        if (hyv[hh] && z < nz) {
+            const Pack<T, VX> p = ldp<T, VX>(cur + (size_t)z * pp + (size_t)hy[hh] * px + x0);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = decode<ST>(p.v[v], h.sc);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
+        }
+    };
+    auto ldhx = [&](int z) -> float {
+        return (hxv && z < nz) ? decode<ST>(cur[(size_t)z * pp + (size_t)hxy * px + hxx], h.sc)
+                               : 0.0f;
+    };
+
+    float q[RY][9][VX];
+#pragma unroll
+    for (int j = 0; j < RY; ++j)
+#pragma unroll
+        for (int k = 0; k < 8; ++k) ld3(cur, zb - 4 + k, yj[j], h.sc, q[j][k]);
+    float la[RY][VX], pv[RY][VX], cv[RY][VX], yh[2][VX];
+#pragma unroll
+    for (int j = 0; j < RY; ++j) {
+        ld3(cur, zb + 4, yj[j], h.sc, la[j]);
+        ld3(prv, zb, yj[j], h.sp, pv[j]);
+        ldc3(zb, yj[j], cv[j]);
+    }
+    ldhy(zb, 0, yh[0]);
+    ldhy(zb, 1, yh[1]);
+    float xh = ldhx(zb);
+    float bmax = 0.0f;
+
+    for (int z = zb; z < ze; ++z) {
+        float pc[RY][VX], cc[RY][VX], yhc[2][VX];
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                q[j][8][v] = la[j][v];
+                pc[j][v] = pv[j][v];
+                cc[j][v] = cv[j][v];
+            }
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int v = 0; v < VX; ++v) yhc[hh][v] = yh[hh][v];
+        const float xhc = xh;
+        if (z + 1 < ze) {
+#pragma unroll
+            for (int j = 0; j < RY; ++j) {
+                ld3(cur, z + 5, yj[j], h.sc, la[j]);
+                ld3(prv, z + 1, yj[j], h.sp, pv[j]);
+                ldc3(z + 1, yj[j], cv[j]);
+            }
+            ldhy(z + 1, 0, yh[0]);
+            ldhy(z + 1, 1, yh[1]);
+            xh = ldhx(z + 1);
+        }
+        float *P = pl[z & 1];
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+#pragma unroll
+            for (int v = 0; v < VX; ++v) P[(wy + 4 * j + 4) * LW + 4 + lane * VX + v] = q[j][4][v];
+#pragma unroll
+        for (int hh = 0; hh < 2; ++hh)
+#pragma unroll
+            for (int v = 0; v < VX; ++v) P[hyslot[hh] + v] = yhc[hh][v];
+        if (hxl) P[hxslot] = xhc;
+        __syncthreads();
+        const float gzz = a.gz[z];
+#pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            float nw[VX], lp[VX], G[VX];
+#pragma unroll
+            for (int v = 0; v < VX; ++v) {
+                const int li = (wy + 4 * j + 4) * LW + 4 + lane * VX + v;
+                const float lx = stencil_taps(P[li - 4], P[li - 3], P[li - 2], P[li - 1], P[li + 1],
+                                              P[li + 2], P[li + 3], P[li + 4]);
+                const float lyv = stencil_taps(P[li - 4 * LW], P[li - 3 * LW], P[li - 2 * LW],
+                                               P[li - LW], P[li + LW], P[li + 2 * LW],
+                                               P[li + 3 * LW], P[li + 4 * LW]);
+                const float lz = stencil_taps(q[j][0][v], q[j][1][v], q[j][2][v], q[j][3][v],
+                                              q[j][5][v], q[j][6][v], q[j][7][v], q[j][8][v]);
+                const float lap = fmaf(3.0f * kA0, q[j][4][v], lz + (lyv + lx));
+                G[v] = (gzz * gyv[j]) * gxv[v];
+                nw[v] = leapfrog(G[v], q[j][4][v], cc[j][v], lap, pc[j][v]);
+                lp[v] = lap;
+            }
+            finish_cells<ST, VX, MODE>(a, h, z, yj[j], x0, lane_in && yin[j],
+                                       (size_t)z * pp + (size_t)yj[j] * px + x0, nw, lp, cc[j],
+                                       G, inj, bmax);
+        }
+#pragma unroll
+        for (int j = 0; j < RY; ++j)
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+#pragma unroll
+                for (int v = 0; v < VX; ++v) q[j][k][v] = q[j][k + 1][v];
+    }
+    if constexpr (ST != kF32) block_max_to<256>(&a.meta[4 + (int)((a.n + 1) & 3)], bmax, red);
+}
+
+// --------------------------------------------------------------------------
+// Set-up and utility kernels
+// --------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t val)
+{
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) p[i] = val;
+}
+
+// c = (v dt/h)^2 rounded from FP64 to FP32, padded; also the velocity range
+// (max as float bits) and a flag for non-positive or non-finite values.
+__global__ void k_model_c(const float *__restrict__ v, float *__restrict__ c, int64_t nrows,
+                          int32_t nx, int32_t px, double r, uint32_t *scratch)
+{
+    uint32_t vmax = 0, bad = 0;
+    const size_t total = (size_t)nrows * nx;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        const size_t rw = i / (size_t)nx, x = i - rw * (size_t)nx;
+        const float vi = v[i];
+        if (!(vi > 0.0f) || !(vi < 3.0e38f)) bad = 1;
+        vmax = max(vmax, __float_as_uint(fabsf(vi)));
+        const double qq = (double)vi * r;
+        c[rw * (size_t)px + x] = (float)(qq * qq);
+    }
+    for (int off = 32; off >= 1; off >>= 1) {
+        vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off, 64));
+        bad |= (uint32_t)__shfl_xor((int)bad, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        atomicMax(&scratch[0], vmax);
+        if (bad) atomicOr(&scratch[1], 1u);
+    }
+}
+
+// First source addition of a shot into the zeroed level-0 field (+ the
+// storage exponent and magnitude of levels 0 and -1).
+template <int ST>
+__global__ void k_begin(void *cur, int64_t src_off, float amp, const float *wavelet,
+                        int32_t *meta)
+{
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    using T = typename Stor<ST>::T;
+    const float x0 = amp * wavelet[0];
+    if constexpr (ST == kF32) {
+        ((T *)cur)[src_off] = x0;
+    } else {
+        const int e0 = storage_exponent(fabsf(x0));
+        ((T *)cur)[src_off] = encode<ST>(x0, pow2i(-e0));
+        meta[0] = e0;
+        meta[3] = 0;
+        meta[4 + 0] = (int32_t)__float_as_uint(fabsf(x0));
+        meta[4 + 1] = 0;
+        meta[4 + 2] = 0;
+        meta[4 + 3] = 0;
+    }
+}
+
+template <int ST>
+__global__ void k_get_field(const void *buf, float *__restrict__ out, int64_t nrows, int32_t nx,
+                            int32_t px, const int32_t *meta, int32_t level_slot)
+{
+    using T = typename Stor<ST>::T;
+    float s = 1.0f;
+    if constexpr (ST != kF32) s = pow2i(meta[level_slot]);
+    const size_t total = (size_t)nrows * nx;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        const size_t rw = i / (size_t)nx, x = i - rw * (size_t)nx;
+        out[i] = decode<ST>(((const T *)buf)[rw * (size_t)px + x], s);
+    }
+}
+
+// max |x| over a dense array, folded into *slot as float bits.
+__global__ void k_absmax(const float *__restrict__ x, size_t n, uint32_t *slot)
+{
+    float m = 0.0f;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n; i += stride) m = fmaxf(m, fabsf(x[i]));
+    for (int off = 32; off >= 1; off >>= 1) m = fmaxf(m, __shfl_xor(m, off, 64));
+    if ((threadIdx.x & 63) == 0) atomicMax(slot, __float_as_uint(m));
+}
+
+// Dense FP32 -> padded stored field; 16-bit storage takes its exponent from
+// the magnitude in meta[4 + slot] and records it in meta[slot].
+template <int ST>
+__global__ void k_set_field(const float *__restrict__ in, void *buf, int64_t nrows, int32_t nx,
+                            int32_t px, int32_t *meta, int32_t slot)
+{
+    using T = typename Stor<ST>::T;
+    float inv = 1.0f;
+    if constexpr (ST != kF32) {
+        const int e = storage_exponent(__uint_as_float((uint32_t)meta[4 + slot]));
+        inv = pow2i(-e);
+        if (blockIdx.x == 0 && threadIdx.x == 0) meta[slot] = e;
+    }
+    const size_t total = (size_t)nrows * px;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        const size_t rw = i / (size_t)px, x = i - rw * (size_t)px;
+        const float v = x < (size_t)nx ? in[rw * (size_t)nx + x] : 0.0f;
+        ((T *)buf)[i] = encode<ST>(v, inv);
+    }
+}
+
+// grad_v += dJ/dc * 2c/v with v = (h/dt) sqrt(c): 2 g dt / (h sqrt(c)).
+__global__ void k_grad_finish(const double *__restrict__ g, const float *__restrict__ c,
+                              double *__restrict__ grad_v, int64_t nrows, int32_t nx, int32_t px,
+                              double two_dt_over_h)
+{
+    const size_t total = (size_t)nrows * nx;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        const size_t rw = i / (size_t)nx, x = i - rw * (size_t)nx;
+        const size_t p = rw * (size_t)px + x;
+        grad_v[i] += g[p] * two_dt_over_h / sqrt((double)c[p]);
+    }
+}
+
+// --------------------------------------------------------------------------
+// Host launchers
+// --------------------------------------------------------------------------
+static int grid_blocks(size_t n, int threads)
+{
+    size_t b = (n + threads - 1) / threads;
+    if (b > 8192) b = 8192;
+    if (b < 1) b = 1;
+    return (int)b;
+}
+
+hipError_t launch_fill_u32(void *p, size_t nwords, uint32_t val, hipStream_t s)
+{
+    if (nwords == 0) return hipSuccess;
+    hipLaunchKernelGGL(k_fill_u32, dim3(grid_blocks(nwords, 256)), dim3(256), 0, s,
+                       (uint32_t *)p, nwords, val);
+    return hipGetLastError();
+}
+
+hipError_t launch_model_c(const float *v, float *c, int64_t nrows, int32_t nx, int32_t px,
+                          double r, uint32_t *scratch, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_model_c, dim3(grid_blocks((size_t)nrows * nx, 256)), dim3(256), 0, s,
+                       v, c, nrows, nx, px, r, scratch);
+    return hipGetLastError();
+}
+
+hipError_t launch_begin(int storage, void *cur, int64_t src_off, float amp,
+                        const float *wavelet, int32_t *meta, hipStream_t s)
+{
+    switch (storage) {
+    case kF32: hipLaunchKernelGGL(k_begin<kF32>, dim3(1), dim3(64), 0, s, cur, src_off, amp, wavelet, meta); break;
+    case kF16: hipLaunchKernelGGL(k_begin<kF16>, dim3(1), dim3(64), 0, s, cur, src_off, amp, wavelet, meta); break;
+    default: hipLaunchKernelGGL(k_begin<kBF16>, dim3(1), dim3(64), 0, s, cur, src_off, amp, wavelet, meta); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_get_field(int storage, const void *buf, float *out, int64_t nrows, int32_t nx,
+                            int32_t px, const int32_t *meta, int32_t level_slot, hipStream_t s)
+{
+    const dim3 g(grid_blocks((size_t)nrows * nx, 256)), b(256);
+    switch (storage) {
+    case kF32: hipLaunchKernelGGL(k_get_field<kF32>, g, b, 0, s, buf, out, nrows, nx, px, meta, level_slot); break;
+    case kF16: hipLaunchKernelGGL(k_get_field<kF16>, g, b, 0, s, buf, out, nrows, nx, px, meta, level_slot); break;
+    default: hipLaunchKernelGGL(k_get_field<kBF16>, g, b, 0, s, buf, out, nrows, nx, px, meta, level_slot); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_set_field(int storage, const float *in, void *buf, int64_t nrows, int32_t nx,
+                            int32_t px, int32_t *meta, int32_t slot, hipStream_t s)
+{
+    if (storage != kF32) {
+        hipError_t e = launch_fill_u32(&meta[4 + slot], 1, 0u, s);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k_absmax, dim3(grid_blocks((size_t)nrows * nx, 256)), dim3(256), 0, s,
+                           in, (size_t)nrows * nx, (uint32_t *)&meta[4 + slot]);
+        e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    const dim3 g(grid_blocks((size_t)nrows * px, 256)), b(256);
+    switch (storage) {
+    case kF32: hipLaunchKernelGGL(k_set_field<kF32>, g, b, 0, s, in, buf, nrows, nx, px, meta, slot); break;
+    case kF16: hipLaunchKernelGGL(k_set_field<kF16>, g, b, 0, s, in, buf, nrows, nx, px, meta, slot); break;
+    default: hipLaunchKernelGGL(k_set_field<kBF16>, g, b, 0, s, in, buf, nrows, nx, px, meta, slot); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, int64_t nrows,
+                              int32_t nx, int32_t px, double two_dt_over_h, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_grad_finish, dim3(grid_blocks((size_t)nrows * nx, 256)), dim3(256), 0,
+                       s, g, c, grad_v, nrows, nx, px, two_dt_over_h);
+    return hipGetLastError();
+}
+
+// Tile shapes.  2D: one wave, 64*VX columns by zc rows.  3D: four waves,
+// (64*VX) x (4*RY) by zc planes.  (Overridable at build time for tuning.)
+#ifndef FD_2D_VX
+#define FD_2D_VX 1
+#endif
+#ifndef FD_2D_ZC
+#define FD_2D_ZC 16
+#endif
+#ifndef FD_3D_VX32
+#define FD_3D_VX32 1
+#endif
+#ifndef FD_3D_RY32
+#define FD_3D_RY32 4
+#endif
+#ifndef FD_3D_VX16
+#define FD_3D_VX16 2
+#endif
+#ifndef FD_3D_RY16
+#define FD_3D_RY16 4
+#endif
+#ifndef FD_3D_ZC
+#define FD_3D_ZC 64
+#endif
+constexpr int k2dVX = FD_2D_VX;
+constexpr int k3dVX32 = FD_3D_VX32, k3dRY32 = FD_3D_RY32;   // FP32 fields
+constexpr int k3dVX16 = FD_3D_VX16, k3dRY16 = FD_3D_RY16;   // 16-bit fields
+
+void plan_tiles(StepArgs &a, int ndim, int storage)
+{
+    if (ndim == 2) {
+        const int TX = 64 * k2dVX;
+        a.zc = FD_2D_ZC;
+        a.tiles_x = (a.nx + TX - 1) / TX;
+        a.tiles_y = 1;
+        a.tiles_z = (a.nz + a.zc - 1) / a.zc;
+    } else {
+        const int VX = storage == kF32 ? k3dVX32 : k3dVX16;
+        const int RY = storage == kF32 ? k3dRY32 : k3dRY16;
+        const int TX = 64 * VX, TY = 4 * RY;
+        a.zc = FD_3D_ZC;
+        a.tiles_x = (a.nx + TX - 1) / TX;
+        a.tiles_y = (a.ny + TY - 1) / TY;
+        a.tiles_z = (a.nz + a.zc - 1) / a.zc;
+    }
+}
+
+template <int ST, int MODE>
+static void launch3d(const StepArgs &a, int nb, hipStream_t s)
+{
+    if constexpr (ST == kF32)
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX32, k3dRY32, MODE>), dim3(nb), dim3(256), 0, s, a);
+    else
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX16, k3dRY16, MODE>), dim3(nb), dim3(256), 0, s, a);
+}
+
+hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t s)
+{
+    plan_tiles(a, ndim, storage);
+    const int nb = a.tiles_x * a.tiles_y * a.tiles_z;
+    if (ndim == 2) {
+        const dim3 g(nb), b(64);
+        if (storage == kF32) {
+            if (mode == kFwd) hipLaunchKernelGGL((k_step2d<kF32, k2dVX, kFwd>), g, b, 0, s, a);
+            else if (mode == kFwdLap) hipLaunchKernelGGL((k_step2d<kF32, k2dVX, kFwdLap>), g, b, 0, s, a);
+            else hipLaunchKernelGGL((k_step2d<kF32, k2dVX, kAdj>), g, b, 0, s, a);
+        } else if (storage == kF16) {
+            hipLaunchKernelGGL((k_step2d<kF16, k2dVX, kFwd>), g, b, 0, s, a);
+        } else {
+            hipLaunchKernelGGL((k_step2d<kBF16, k2dVX, kFwd>), g, b, 0, s, a);
+        }
+    } else {
+        if (storage == kF32) {
+            if (mode == kFwd) launch3d<kF32, kFwd>(a, nb, s);
+            else if (mode == kFwdLap) launch3d<kF32, kFwdLap>(a, nb, s);
+            else launch3d<kF32, kAdj>(a, nb, s);
+        } else if (storage == kF16) {
+            launch3d<kF16, kFwd>(a, nb, s);
+        } else {
+            launch3d<kBF16, kFwd>(a, nb, s);
+        }
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_step_batch2d(Batch2D &b, hipStream_t s)
+{
+    int total = 0;
+    for (int i = 0; i < b.count; ++i) {
+        plan_tiles(b.it[i], 2, kF32);
+        b.begin[i] = total;
+        total += b.it[i].tiles_x * b.it[i].tiles_z;
+    }
+    b.begin[b.count] = total;
+    if (total == 0) return hipSuccess;
+    hipLaunchKernelGGL((k_step2d_batch<k2dVX>), dim3(total), dim3(64), 0, s, b);
+    return hipGetLastError();
+}
+
+}  // namespace fdk

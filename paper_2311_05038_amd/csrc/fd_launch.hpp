@@ -1,0 +1,38 @@
+// Host-side launchers of the device kernels (internal to the library).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "fd_device.hpp"
+
+namespace fdk {
+
+constexpr int kBatchMax = 16;
+
+// Kernel-argument table of one batched launch (passed by value, < 4 KiB).
+struct Batch2D {
+    int32_t count;
+    int32_t begin[kBatchMax + 1];
+    StepArgs it[kBatchMax];
+};
+static_assert(sizeof(Batch2D) <= 4096, "batched step arguments must fit the kernel-argument segment");
+
+// Fills tiles_x/y/z and zc of `a` for the kernel variant that runs it.
+void plan_tiles(StepArgs &a, int ndim, int storage);
+
+hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t s);
+hipError_t launch_step_batch2d(Batch2D &b, hipStream_t s);
+hipError_t launch_fill_u32(void *p, size_t nwords, uint32_t val, hipStream_t s);
+hipError_t launch_model_c(const float *v, float *c, int64_t nrows, int32_t nx, int32_t px,
+                          double r, uint32_t *scratch, hipStream_t s);
+hipError_t launch_begin(int storage, void *cur, int64_t src_off, float amp,
+                        const float *wavelet, int32_t *meta, hipStream_t s);
+hipError_t launch_get_field(int storage, const void *buf, float *out, int64_t nrows, int32_t nx,
+                            int32_t px, const int32_t *meta, int32_t level_slot, hipStream_t s);
+hipError_t launch_set_field(int storage, const float *in, void *buf, int64_t nrows, int32_t nx,
+                            int32_t px, int32_t *meta, int32_t slot, hipStream_t s);
+hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, int64_t nrows,
+                              int32_t nx, int32_t px, double two_dt_over_h, hipStream_t s);
+
+}  // namespace fdk

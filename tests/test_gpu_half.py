@@ -1,0 +1,113 @@
+"""GPU 16-bit field storage (binary16 / bfloat16 codes with one power-of-two
+scale per field, FP32 arithmetic) against the oracle.
+
+The quantised time loop is sensitive to the order of FP32 operations: a value
+that lands within one FP32 ulp of a 16-bit rounding midpoint may round either
+way, and such a flip then perturbs its neighbours, so two correct
+implementations drift apart over many steps until they differ by about the
+quantisation error itself.  The bars are therefore:
+  * code-level parity over a few steps from identical stored states (set
+    through fd_set_wavefield on the GPU, given to the emulation directly):
+    every decoded value equal, or off by one 16-bit ulp at a small fraction
+    of cells;
+  * set/get round trip bit-exact against the oracle's encoder;
+  * whole shots: the error against the FP64 oracle is stated and bounded,
+    and is of the same size as the emulation's own error."""
+import numpy as np
+import pytest
+import torch
+
+import fd_inputs as fi
+import oracle
+from helpers import receivers_of, rel_l2, run, setup
+
+pytestmark = pytest.mark.gpu
+
+MANT = {1: 10, 2: 7}          # stored significand bits (without the implicit one)
+FP64_TOL = {1: 1e-2, 2: 8e-2}
+
+
+def _cases():
+    return [fi.surface2d(70, 133, 200, seed=12), fi.layered3d(nx=72, ny=40, nz=45, nt=70)]
+
+
+def _start_state(p, k):
+    """A physical (prev, cur) pair: the FP64 oracle after k steps, in FP32."""
+    v = p.velocity()
+    out = oracle.forward(oracle.grid_of(p), v.reshape(p.nz, p.ny, p.nx), p.wavelet(), k, p.src,
+                         p.rec_index())
+    return v, out["prev"].astype(np.float32), out["cur"].astype(np.float32)
+
+
+def _ulp_of(x, storage, e):
+    """One unit in the last place of the 16-bit code of x * 2^-e, times 2^e."""
+    q = np.abs(x.astype(np.float64)) * 2.0 ** -e
+    ex = np.floor(np.log2(np.maximum(q, 2.0 ** -14 if storage == 1 else 2.0 ** -126)))
+    return 2.0 ** (ex - MANT[storage]) * 2.0 ** e
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("case", [0, 1])
+@pytest.mark.parametrize("nsteps", [1, 3])
+def test_code_level_parity_from_identical_states(storage, case, nsteps):
+    import paper_2311_05038_amd as fd
+    p = _cases()[case]
+    print(f"case {p.name} storage={storage} nsteps={nsteps}", flush=True)
+    v, prev, cur = _start_state(p, 40)
+    ps = p.scaled(nt=nsteps)
+    model, state, _ = setup(ps, v, storage=storage)
+    wav = p.wavelet()[40:40 + nsteps].copy()
+    shot = fd.Shot(p.src, torch.from_numpy(wav).cuda(), receivers_of(p))
+    state.set_wavefield(0, torch.from_numpy(cur.ravel()).cuda())
+    state.set_wavefield(1, torch.from_numpy(prev.ravel()).cuda())
+    tr = torch.zeros((nsteps, p.receivers.count), device="cuda")
+    for n in range(nsteps):
+        state.step(shot, n, tr[n])
+    got = state.wavefield(0).cpu().numpy().reshape(-1)
+    emu = oracle.forward_half(oracle.grid_of(ps), storage, v.reshape(p.nz, p.ny, p.nx), wav,
+                              nsteps, p.src, p.rec_index(), init_prev=prev, init_cur=cur)
+    ref = emu["cur"].reshape(-1)
+    diff = np.abs(got.astype(np.float64) - ref)
+    e = int(np.floor(np.log2(np.abs(ref).max()))) - 11
+    # one step: identical inputs, so at most one code flip per value; later
+    # steps also see their neighbours' flips through the stencil
+    tol = _ulp_of(ref, storage, e) * (1 if nsteps == 1 else 8)
+    frac = float(np.mean(diff > 0))
+    print(f"mismatch fraction {frac:.2e}, max diff/ulp {float((diff / tol).max()):.2f}", flush=True)
+    assert np.all(diff <= tol * 1.0000001)
+    assert frac <= 2e-3 * nsteps
+    # traces are the FP32 values before quantisation
+    tr_tol = 1e-5 if nsteps == 1 else (1e-4 if storage == 1 else 1e-3)
+    assert rel_l2(tr.cpu().numpy(), emu["traces"]) <= tr_tol
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_set_get_round_trip_matches_encoder(storage):
+    p = fi.layered3d(nx=70, ny=33, nz=21, nt=4)
+    x = (np.random.default_rng(9).standard_normal(p.shape) * 1e-7).astype(np.float32)
+    x[3, 4, 5] = 0.0
+    model, state, _ = setup(p, storage=storage)
+    state.set_wavefield(0, torch.from_numpy(x.ravel()).cuda())
+    got = state.wavefield(0).cpu().numpy()
+    e = int(np.frexp(np.float32(np.abs(x).max()))[1]) - 1 - 11
+    ref = oracle.decode(storage, oracle.encode(storage, np.ldexp(x, -e))).astype(np.float64) * 2.0 ** e
+    np.testing.assert_array_equal(got.astype(np.float64), ref)
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("case", [0, 1])
+def test_whole_shot_error_against_fp64_is_bounded(storage, case):
+    p = _cases()[case]
+    print(f"case {p.name} storage={storage}", flush=True)
+    v = p.velocity()
+    tr, cur = run(p, v, storage=storage)
+    g = oracle.grid_of(p)
+    vv = v.reshape(p.nz, p.ny, p.nx)
+    emu = oracle.forward_half(g, storage, vv, p.wavelet(), p.nt, p.src, p.rec_index())
+    ref = oracle.forward(g, vv, p.wavelet(), p.nt, p.src, p.rec_index())
+    e_gpu = max(rel_l2(tr, ref["traces"]), rel_l2(cur, ref["cur"].reshape(cur.shape)))
+    e_emu = max(rel_l2(emu["traces"], ref["traces"]),
+                rel_l2(emu["cur"], ref["cur"]))
+    print(f"error vs fp64: gpu {e_gpu:.3e}  emulation {e_emu:.3e}", flush=True)
+    assert e_gpu <= FP64_TOL[storage]
+    assert e_gpu <= 1.5 * e_emu + 1e-4
