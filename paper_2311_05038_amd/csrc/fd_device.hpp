@@ -78,6 +78,48 @@ __device__ __forceinline__ void stp(T *p, const Pack<T, VX> &x)
     *reinterpret_cast<Pack<T, VX> *>(p) = x;
 }
 
+// Raw integer vector of a given byte size, for the non-temporal builtins.
+template <int B> struct Raw;
+template <> struct Raw<2> { using type = unsigned short; };
+template <> struct Raw<4> { using type = unsigned int; };
+template <> struct Raw<8> { typedef unsigned int type __attribute__((ext_vector_type(2))); };
+template <> struct Raw<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
+template <> struct Raw<32> { typedef unsigned int type __attribute__((ext_vector_type(8))); };
+
+#ifndef FD_NT
+#define FD_NT 1
+#endif
+
+// Streaming (read-once / write-once) accesses: Pold, c and Pnew are touched
+// once per step, so they are marked non-temporal to leave the L2 to the
+// current field, whose planes neighbouring tiles re-read as halos.
+template <typename T, int VX>
+__device__ __forceinline__ Pack<T, VX> ldp_stream(const T *p)
+{
+#if FD_NT
+    using R = typename Raw<sizeof(T) * VX>::type;
+    const R r = __builtin_nontemporal_load(reinterpret_cast<const R *>(p));
+    Pack<T, VX> o;
+    __builtin_memcpy(&o, &r, sizeof(o));
+    return o;
+#else
+    return ldp<T, VX>(p);
+#endif
+}
+
+template <typename T, int VX>
+__device__ __forceinline__ void stp_stream(T *p, const Pack<T, VX> &x)
+{
+#if FD_NT
+    using R = typename Raw<sizeof(T) * VX>::type;
+    R r;
+    __builtin_memcpy(&r, &x, sizeof(r));
+    __builtin_nontemporal_store(r, reinterpret_cast<R *>(p));
+#else
+    stp<T, VX>(p, x);
+#endif
+}
+
 template <int ST>
 __device__ __forceinline__ float decode(typename Stor<ST>::T q, float scale)
 {

@@ -19,7 +19,7 @@ namespace fdk {
 // --------------------------------------------------------------------------
 // Epilogue shared by 2D and 3D: receivers, source, padding, store.
 // --------------------------------------------------------------------------
-template <int ST, int VX, int MODE>
+template <int ST, int VX, int MODE, bool STREAM>
 __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h, int z, int y,
                                              int x0, bool store_ok, size_t off, float (&nw)[VX],
                                              const float (&lp)[VX], const float (&cc)[VX],
@@ -68,7 +68,10 @@ __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h
     Pack<T, VX> o;
 #pragma unroll
     for (int v = 0; v < VX; ++v) o.v[v] = encode<ST>(nw[v], h.sn_inv);
-    stp<T, VX>(prv + off, o);
+    if constexpr (STREAM)
+        stp_stream<T, VX>(prv + off, o);
+    else
+        stp<T, VX>(prv + off, o);
     if constexpr (MODE == kFwdLap) {
         Pack<float, VX> L;
 #pragma unroll
@@ -212,7 +215,7 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
             nw[v] = leapfrog(G[v], q[4][v], cc[v], lap, pc[v]);
             lp[v] = lap;
         }
-        finish_cells<ST, VX, MODE>(a, h, z, 0, x0, lane_in, (size_t)z * px + x0, nw, lp, cc, G,
+        finish_cells<ST, VX, MODE, false>(a, h, z, 0, x0, lane_in, (size_t)z * px + x0, nw, lp, cc, G,
                                    inj, bmax);
 #pragma unroll
         for (int k = 0; k < 8; ++k)
@@ -258,13 +261,14 @@ __global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
 // --------------------------------------------------------------------------
 // 3D
 // --------------------------------------------------------------------------
-template <int ST, int VX, int RY, int MODE>
-__global__ __launch_bounds__(256) void k_step3d(StepArgs a)
+template <int ST, int VX, int RY, int NW, int MODE>
+__global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
 {
     using T = typename Stor<ST>::T;
-    constexpr int TX = 64 * VX, TY = 4 * RY, LW = TX + 8, LH = TY + 8;
+    static_assert(NW == 2 || NW == 4 || NW == 8, "waves per block");
+    constexpr int TX = 64 * VX, TY = NW * RY, LW = TX + 8, LH = TY + 8, HH = 8 / NW;
     __shared__ float pl[2][LH * LW];
-    __shared__ float red[4];
+    __shared__ float red[NW];
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
     const int nb = a.tiles_x * a.tiles_y * a.tiles_z;
     const int t = xcd_tile(blockIdx.x, nb);
@@ -289,7 +293,7 @@ __global__ __launch_bounds__(256) void k_step3d(StepArgs a)
     float gyv[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-        yj[j] = yb + wy + 4 * j;
+        yj[j] = yb + wy + NW * j;
         yin[j] = yj[j] < ny;
         gyv[j] = yin[j] ? a.gy[yj[j]] : 0.0f;
     }
@@ -297,12 +301,12 @@ __global__ __launch_bounds__(256) void k_step3d(StepArgs a)
 #pragma unroll
     for (int v = 0; v < VX; ++v) gxv[v] = (x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
 
-    // y-halo rows handled by this thread: k = wy + 4 hh, hh = 0, 1.
-    int hy[2], hyslot[2];
-    bool hyv[2];
+    // y-halo rows handled by this thread: k = wy + NW hh, hh < 8 / NW.
+    int hy[HH], hyslot[HH];
+    bool hyv[HH];
 #pragma unroll
-    for (int hh = 0; hh < 2; ++hh) {
-        const int k = wy + 4 * hh;
+    for (int hh = 0; hh < HH; ++hh) {
+        const int k = wy + NW * hh;
         const int ly = k < 4 ? k - 4 : TY + k - 4;
         hy[hh] = yb + ly;
         hyv[hh] = hy[hh] >= 0 && hy[hh] < ny && lane_in;
@@ -329,9 +333,19 @@ __global__ __launch_bounds__(256) void k_step3d(StepArgs a)
             for (int v = 0; v < VX; ++v) o[v] = 0.0f;
         }
     };
+    auto ld3nt = [&](const T *base, int z, int y, float s, float (&o)[VX]) {
+        if (z < nz && y < ny && lane_in) {
+            const Pack<T, VX> p = ldp_stream<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = decode<ST>(p.v[v], s);
+        } else {
+#pragma unroll
+            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
+        }
+    };
     auto ldc3 = [&](int z, int y, float (&o)[VX]) {
         if (z < nz && y < ny && lane_in) {
-            const Pack<float, VX> p = ldp<float, VX>(a.c + (size_t)z * pp + (size_t)y * px + x0);
+            const Pack<float, VX> p = ldp_stream<float, VX>(a.c + (size_t)z * pp + (size_t)y * px + x0);
 #pragma unroll
             for (int v = 0; v < VX; ++v) o[v] = p.v[v];
         } else {
@@ -359,20 +373,20 @@ __global__ __launch_bounds__(256) void k_step3d(StepArgs a)
     for (int j = 0; j < RY; ++j)
 #pragma unroll
         for (int k = 0; k < 8; ++k) ld3(cur, zb - 4 + k, yj[j], h.sc, q[j][k]);
-    float la[RY][VX], pv[RY][VX], cv[RY][VX], yh[2][VX];
+    float la[RY][VX], pv[RY][VX], cv[RY][VX], yh[HH][VX];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         ld3(cur, zb + 4, yj[j], h.sc, la[j]);
-        ld3(prv, zb, yj[j], h.sp, pv[j]);
+        ld3nt(prv, zb, yj[j], h.sp, pv[j]);
         ldc3(zb, yj[j], cv[j]);
     }
-    ldhy(zb, 0, yh[0]);
-    ldhy(zb, 1, yh[1]);
+#pragma unroll
+    for (int hh = 0; hh < HH; ++hh) ldhy(zb, hh, yh[hh]);
     float xh = ldhx(zb);
     float bmax = 0.0f;
 
     for (int z = zb; z < ze; ++z) {
-        float pc[RY][VX], cc[RY][VX], yhc[2][VX];
+        float pc[RY][VX], cc[RY][VX], yhc[HH][VX];
 #pragma unroll
         for (int j = 0; j < RY; ++j)
 #pragma unroll
@@ -382,7 +396,7 @@ __global__ __launch_bounds__(256) void k_step3d(StepArgs a)
                 cc[j][v] = cv[j][v];
             }
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
+        for (int hh = 0; hh < HH; ++hh)
 #pragma unroll
             for (int v = 0; v < VX; ++v) yhc[hh][v] = yh[hh][v];
         const float xhc = xh;
@@ -390,20 +404,20 @@ __global__ __launch_bounds__(256) void k_step3d(StepArgs a)
 #pragma unroll
             for (int j = 0; j < RY; ++j) {
                 ld3(cur, z + 5, yj[j], h.sc, la[j]);
-                ld3(prv, z + 1, yj[j], h.sp, pv[j]);
+                ld3nt(prv, z + 1, yj[j], h.sp, pv[j]);
                 ldc3(z + 1, yj[j], cv[j]);
             }
-            ldhy(z + 1, 0, yh[0]);
-            ldhy(z + 1, 1, yh[1]);
+#pragma unroll
+            for (int hh = 0; hh < HH; ++hh) ldhy(z + 1, hh, yh[hh]);
             xh = ldhx(z + 1);
         }
         float *P = pl[z & 1];
 #pragma unroll
         for (int j = 0; j < RY; ++j)
 #pragma unroll
-            for (int v = 0; v < VX; ++v) P[(wy + 4 * j + 4) * LW + 4 + lane * VX + v] = q[j][4][v];
+            for (int v = 0; v < VX; ++v) P[(wy + NW * j + 4) * LW + 4 + lane * VX + v] = q[j][4][v];
 #pragma unroll
-        for (int hh = 0; hh < 2; ++hh)
+        for (int hh = 0; hh < HH; ++hh)
 #pragma unroll
             for (int v = 0; v < VX; ++v) P[hyslot[hh] + v] = yhc[hh][v];
         if (hxl) P[hxslot] = xhc;
@@ -414,7 +428,7 @@ __global__ __launch_bounds__(256) void k_step3d(StepArgs a)
             float nw[VX], lp[VX], G[VX];
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
-                const int li = (wy + 4 * j + 4) * LW + 4 + lane * VX + v;
+                const int li = (wy + NW * j + 4) * LW + 4 + lane * VX + v;
                 const float lx = stencil_taps(P[li - 4], P[li - 3], P[li - 2], P[li - 1], P[li + 1],
                                               P[li + 2], P[li + 3], P[li + 4]);
                 const float lyv = stencil_taps(P[li - 4 * LW], P[li - 3 * LW], P[li - 2 * LW],
@@ -427,7 +441,7 @@ __global__ __launch_bounds__(256) void k_step3d(StepArgs a)
                 nw[v] = leapfrog(G[v], q[j][4][v], cc[j][v], lap, pc[j][v]);
                 lp[v] = lap;
             }
-            finish_cells<ST, VX, MODE>(a, h, z, yj[j], x0, lane_in && yin[j],
+            finish_cells<ST, VX, MODE, true>(a, h, z, yj[j], x0, lane_in && yin[j],
                                        (size_t)z * pp + (size_t)yj[j] * px + x0, nw, lp, cc[j],
                                        G, inj, bmax);
         }
@@ -438,7 +452,7 @@ __global__ __launch_bounds__(256) void k_step3d(StepArgs a)
 #pragma unroll
                 for (int v = 0; v < VX; ++v) q[j][k][v] = q[j][k + 1][v];
     }
-    if constexpr (ST != kF32) block_max_to<256>(&a.meta[4 + (int)((a.n + 1) & 3)], bmax, red);
+    if constexpr (ST != kF32) block_max_to<64 * NW>(&a.meta[4 + (int)((a.n + 1) & 3)], bmax, red);
 }
 
 // --------------------------------------------------------------------------
@@ -647,7 +661,7 @@ hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, i
 // Tile shapes.  2D: one wave, 64*VX columns by zc rows.  3D: four waves,
 // (64*VX) x (4*RY) by zc planes.  (Overridable at build time for tuning.)
 #ifndef FD_2D_VX
-#define FD_2D_VX 1
+#define FD_2D_VX 2
 #endif
 #ifndef FD_2D_ZC
 #define FD_2D_ZC 16
@@ -664,6 +678,12 @@ hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, i
 #ifndef FD_3D_RY16
 #define FD_3D_RY16 4
 #endif
+#ifndef FD_3D_NW32
+#define FD_3D_NW32 4
+#endif
+#ifndef FD_3D_NW16
+#define FD_3D_NW16 4
+#endif
 #ifndef FD_3D_ZC
 #define FD_3D_ZC 64
 #endif
@@ -675,14 +695,18 @@ void plan_tiles(StepArgs &a, int ndim, int storage)
 {
     if (ndim == 2) {
         const int TX = 64 * k2dVX;
-        a.zc = FD_2D_ZC;
         a.tiles_x = (a.nx + TX - 1) / TX;
+        // Rows per block: FD_2D_ZC, halved while the grid would give fewer
+        // than 2048 blocks (8 per CU), down to 4.
+        a.zc = FD_2D_ZC;
+        while (a.zc > 4 && (int64_t)a.tiles_x * ((a.nz + a.zc - 1) / a.zc) < 2048) a.zc >>= 1;
         a.tiles_y = 1;
         a.tiles_z = (a.nz + a.zc - 1) / a.zc;
     } else {
         const int VX = storage == kF32 ? k3dVX32 : k3dVX16;
         const int RY = storage == kF32 ? k3dRY32 : k3dRY16;
-        const int TX = 64 * VX, TY = 4 * RY;
+        const int NW = storage == kF32 ? FD_3D_NW32 : FD_3D_NW16;
+        const int TX = 64 * VX, TY = NW * RY;
         a.zc = FD_3D_ZC;
         a.tiles_x = (a.nx + TX - 1) / TX;
         a.tiles_y = (a.ny + TY - 1) / TY;
@@ -694,9 +718,11 @@ template <int ST, int MODE>
 static void launch3d(const StepArgs &a, int nb, hipStream_t s)
 {
     if constexpr (ST == kF32)
-        hipLaunchKernelGGL((k_step3d<ST, k3dVX32, k3dRY32, MODE>), dim3(nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX32, k3dRY32, FD_3D_NW32, MODE>), dim3(nb),
+                           dim3(64 * FD_3D_NW32), 0, s, a);
     else
-        hipLaunchKernelGGL((k_step3d<ST, k3dVX16, k3dRY16, MODE>), dim3(nb), dim3(256), 0, s, a);
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX16, k3dRY16, FD_3D_NW16, MODE>), dim3(nb),
+                           dim3(64 * FD_3D_NW16), 0, s, a);
 }
 
 hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t s)

@@ -68,13 +68,18 @@ def test_code_level_parity_from_identical_states(storage, case, nsteps):
                               nsteps, p.src, p.rec_index(), init_prev=prev, init_cur=cur)
     ref = emu["cur"].reshape(-1)
     diff = np.abs(got.astype(np.float64) - ref)
-    e = int(np.floor(np.log2(np.abs(ref).max()))) - 11
-    # one step: identical inputs, so at most one code flip per value; later
-    # steps also see their neighbours' flips through the stencil
-    tol = _ulp_of(ref, storage, e) * (1 if nsteps == 1 else 8)
-    frac = float(np.mean(diff > 0))
-    print(f"mismatch fraction {frac:.2e}, max diff/ulp {float((diff / tol).max()):.2f}", flush=True)
-    assert np.all(diff <= tol * 1.0000001)
+    amax = np.abs(ref).max()
+    e = int(np.floor(np.log2(amax))) - 11
+    # One step from identical codes: a value may round to the neighbouring
+    # code (one ulp), and FP32 rounding of the update, whose terms cancel far
+    # ahead of the wavefront, is bounded at the field's scale (2^-20 max|P|);
+    # later steps also see their neighbours' flips through the stencil.
+    k = 1 if nsteps == 1 else 8
+    tol = _ulp_of(ref, storage, e) * k + k * 2.0 ** -20 * amax
+    big = np.abs(ref) > 2.0 ** -20 * amax
+    frac = float(np.mean(diff[big] > 0))
+    print(f"mismatch fraction {frac:.2e}, max diff/tol {float((diff / tol).max()):.2f}", flush=True)
+    assert np.all(diff <= tol)
     assert frac <= 2e-3 * nsteps
     # traces are the FP32 values before quantisation
     tr_tol = 1e-5 if nsteps == 1 else (1e-4 if storage == 1 else 1e-3)
