@@ -80,7 +80,7 @@ Layout make_layout(const fd_grid &g)
     L.scratch_off = L.gx_off + align_up((size_t)g.nx * 4);
     L.model_bytes = L.scratch_off + kAlign;
     L.meta_off = 2 * L.field;
-    L.state_bytes = L.meta_off + kAlign;
+    L.state_bytes = L.meta_off + align_up(fdk::kMetaWords * 4);
     return L;
 }
 

@@ -45,6 +45,7 @@ struct StepArgs {
     const float *gz, *gy, *gx;  // damping profiles (nz, ny, nx entries)
     int32_t nz, ny, nx, px;
     int32_t zc;           // planes (rows in 2D) per block
+    int32_t vx;           // cells per lane along x (2D tile width 64 * vx)
     int32_t tiles_x, tiles_y, tiles_z;
     int32_t sz, sy, sx;   // source cell
     float amp;            // dt^2 / h^D
@@ -164,30 +165,52 @@ struct HalfCtx {
     float sc, sp, sn_inv;  // decode scale of cur and prev, encode scale of new
 };
 
+// Layout of the 16-bit storage bookkeeping ("meta", in the state buffer):
+// meta[l] (l < 4) is the exponent of time level l mod 4; the largest
+// magnitude of level l is the maximum over kMaxSlots words at
+// meta[kMaxBase + l * kMaxSlots + k] (float bit patterns; blocks fold their
+// maxima into slot blockIdx % kMaxSlots, which spreads the atomics).
+constexpr int kMaxSlots = 64;
+constexpr int kMaxBase = 16;
+constexpr int kMetaWords = kMaxBase + 4 * kMaxSlots;
+
+__device__ __forceinline__ float level_max(const int32_t *meta, int level)
+{
+    uint32_t m = 0;
+#pragma unroll 16
+    for (int k = 0; k < kMaxSlots; ++k) m = max(m, (uint32_t)meta[kMaxBase + level * kMaxSlots + k]);
+    return __uint_as_float(m);
+}
+
 template <int ST>
-__device__ __forceinline__ HalfCtx half_prologue(const StepArgs &a, float inj, bool leader)
+__device__ __forceinline__ HalfCtx half_prologue(const StepArgs &a, float inj, bool block0)
 {
     HalfCtx h{1.0f, 1.0f, 1.0f};
     if constexpr (ST != kF32) {
         const int ic = (int)(a.n & 3), ip = (int)((a.n + 3) & 3);
         const int in = (int)((a.n + 1) & 3), iz = (int)((a.n + 2) & 3);
         const int ec = a.meta[ic], ep = a.meta[ip];
-        float m = fmaxf(__uint_as_float((uint32_t)a.meta[4 + ic]),
-                        __uint_as_float((uint32_t)a.meta[4 + ip]));
+        float m = fmaxf(level_max(a.meta, ic), level_max(a.meta, ip));
         m = fmaxf(m, fabsf(inj));
         const int en = storage_exponent(m);
         h.sc = pow2i(ec);
         h.sp = pow2i(ep);
         h.sn_inv = pow2i(-en);
-        if (leader) {
-            a.meta[in] = en;
-            a.meta[4 + iz] = 0;  // slot of level n+2, filled by the next step
+        if (block0) {
+            if (threadIdx.x == 0) a.meta[in] = en;
+            // slots of level n+2 (not read by this step) are cleared for the next one
+            if (threadIdx.x < kMaxSlots) a.meta[kMaxBase + iz * kMaxSlots + threadIdx.x] = 0;
         }
     }
     return h;
 }
 
-// Block-wide max of non-negative floats, folded into meta by atomicMax on
+__device__ __forceinline__ int32_t *max_slot(int32_t *meta, int level)
+{
+    return &meta[kMaxBase + level * kMaxSlots + (blockIdx.x & (kMaxSlots - 1))];
+}
+
+// Block-wide max of non-negative floats, folded into a slot by atomicMax on
 // the bit pattern (order-independent, hence deterministic).
 template <int NT>
 __device__ __forceinline__ void block_max_to(int32_t *slot, float v, float *red)

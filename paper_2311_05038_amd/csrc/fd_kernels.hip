@@ -234,10 +234,10 @@ __global__ __launch_bounds__(64) void k_step2d(StepArgs a)
     float inj = 0.0f;
     if constexpr (MODE != kAdj)
         if (a.n + 1 < a.nt) inj = a.amp * a.wavelet[a.n + 1];
-    const HalfCtx h = half_prologue<ST>(a, inj, blockIdx.x == 0 && threadIdx.x == 0);
+    const HalfCtx h = half_prologue<ST>(a, inj, blockIdx.x == 0);
     float bmax = 0.0f;
     step2d_tile<ST, VX, MODE>(a, tx, tz, row, h, inj, bmax);
-    if constexpr (ST != kF32) block_max_to<64>(&a.meta[4 + (int)((a.n + 1) & 3)], bmax, nullptr);
+    if constexpr (ST != kF32) block_max_to<64>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax, nullptr);
 }
 
 // Batched 2D FP32 forward step: block b belongs to the item whose tile range
@@ -286,7 +286,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
     float inj = 0.0f;
     if constexpr (MODE != kAdj)
         if (a.n + 1 < a.nt) inj = a.amp * a.wavelet[a.n + 1];
-    const HalfCtx h = half_prologue<ST>(a, inj, blockIdx.x == 0 && threadIdx.x == 0);
+    const HalfCtx h = half_prologue<ST>(a, inj, blockIdx.x == 0);
 
     int yj[RY];
     bool yin[RY];
@@ -452,7 +452,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
 #pragma unroll
                 for (int v = 0; v < VX; ++v) q[j][k][v] = q[j][k + 1][v];
     }
-    if constexpr (ST != kF32) block_max_to<64 * NW>(&a.meta[4 + (int)((a.n + 1) & 3)], bmax, red);
+    if constexpr (ST != kF32) block_max_to<64 * NW>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax, red);
 }
 
 // --------------------------------------------------------------------------
@@ -504,14 +504,11 @@ __global__ void k_begin(void *cur, int64_t src_off, float amp, const float *wave
     if constexpr (ST == kF32) {
         ((T *)cur)[src_off] = x0;
     } else {
+        // the state was cleared: every exponent and magnitude slot is zero
         const int e0 = storage_exponent(fabsf(x0));
         ((T *)cur)[src_off] = encode<ST>(x0, pow2i(-e0));
         meta[0] = e0;
-        meta[3] = 0;
-        meta[4 + 0] = (int32_t)__float_as_uint(fabsf(x0));
-        meta[4 + 1] = 0;
-        meta[4 + 2] = 0;
-        meta[4 + 3] = 0;
+        meta[kMaxBase] = (int32_t)__float_as_uint(fabsf(x0));
     }
 }
 
@@ -531,9 +528,11 @@ __global__ void k_get_field(const void *buf, float *__restrict__ out, int64_t nr
     }
 }
 
-// max |x| over a dense array, folded into *slot as float bits.
-__global__ void k_absmax(const float *__restrict__ x, size_t n, uint32_t *slot)
+// max |x| over a dense array, folded into slots[blockIdx % kMaxSlots] as
+// float bits.
+__global__ void k_absmax(const float *__restrict__ x, size_t n, uint32_t *slots)
 {
+    uint32_t *slot = &slots[blockIdx.x & (kMaxSlots - 1)];
     float m = 0.0f;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
@@ -551,7 +550,7 @@ __global__ void k_set_field(const float *__restrict__ in, void *buf, int64_t nro
     using T = typename Stor<ST>::T;
     float inv = 1.0f;
     if constexpr (ST != kF32) {
-        const int e = storage_exponent(__uint_as_float((uint32_t)meta[4 + slot]));
+        const int e = storage_exponent(level_max(meta, slot));
         inv = pow2i(-e);
         if (blockIdx.x == 0 && threadIdx.x == 0) meta[slot] = e;
     }
@@ -634,10 +633,11 @@ hipError_t launch_set_field(int storage, const float *in, void *buf, int64_t nro
                             int32_t px, int32_t *meta, int32_t slot, hipStream_t s)
 {
     if (storage != kF32) {
-        hipError_t e = launch_fill_u32(&meta[4 + slot], 1, 0u, s);
+        uint32_t *slots = (uint32_t *)&meta[kMaxBase + slot * kMaxSlots];
+        hipError_t e = launch_fill_u32(slots, kMaxSlots, 0u, s);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k_absmax, dim3(grid_blocks((size_t)nrows * nx, 256)), dim3(256), 0, s,
-                           in, (size_t)nrows * nx, (uint32_t *)&meta[4 + slot]);
+                           in, (size_t)nrows * nx, slots);
         e = hipGetLastError();
         if (e != hipSuccess) return e;
     }
@@ -660,23 +660,17 @@ hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, i
 
 // Tile shapes.  2D: one wave, 64*VX columns by zc rows.  3D: four waves,
 // (64*VX) x (4*RY) by zc planes.  (Overridable at build time for tuning.)
-#ifndef FD_2D_VX
-#define FD_2D_VX 2
-#endif
-#ifndef FD_2D_ZC
-#define FD_2D_ZC 16
-#endif
 #ifndef FD_3D_VX32
-#define FD_3D_VX32 1
+#define FD_3D_VX32 4
 #endif
 #ifndef FD_3D_RY32
-#define FD_3D_RY32 4
+#define FD_3D_RY32 2
 #endif
 #ifndef FD_3D_VX16
-#define FD_3D_VX16 2
+#define FD_3D_VX16 4
 #endif
 #ifndef FD_3D_RY16
-#define FD_3D_RY16 4
+#define FD_3D_RY16 1
 #endif
 #ifndef FD_3D_NW32
 #define FD_3D_NW32 4
@@ -687,26 +681,34 @@ hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, i
 #ifndef FD_3D_ZC
 #define FD_3D_ZC 64
 #endif
-constexpr int k2dVX = FD_2D_VX;
 constexpr int k3dVX32 = FD_3D_VX32, k3dRY32 = FD_3D_RY32;   // FP32 fields
 constexpr int k3dVX16 = FD_3D_VX16, k3dRY16 = FD_3D_RY16;   // 16-bit fields
+constexpr int kBatchVX = 2;
 
-void plan_tiles(StepArgs &a, int ndim, int storage)
+// Tile shapes.  3D: NW waves, (64 VX) x (NW RY) cells by zc planes (the
+// defaults come from a sweep of shapes on the 512^3 and 768x768x512 grids).
+// 2D: one wave, 64 VX columns by zc rows; the widest tile and tallest chunk
+// that still give >= 2048 blocks (8 per CU) are taken from
+// (VX, zc) = (2, 16), (2, 8), (1, 8), (1, 4).
+void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
 {
     if (ndim == 2) {
-        const int TX = 64 * k2dVX;
-        a.tiles_x = (a.nx + TX - 1) / TX;
-        // Rows per block: FD_2D_ZC, halved while the grid would give fewer
-        // than 2048 blocks (8 per CU), down to 4.
-        a.zc = FD_2D_ZC;
-        while (a.zc > 4 && (int64_t)a.tiles_x * ((a.nz + a.zc - 1) / a.zc) < 2048) a.zc >>= 1;
+        static const int cand[4][2] = {{2, 16}, {2, 8}, {1, 8}, {1, 4}};
+        for (int i = 0; i < 4; ++i) {
+            a.vx = cand[i][0];
+            a.zc = cand[i][1];
+            if (batched && a.vx != kBatchVX) continue;
+            a.tiles_x = (a.nx + 64 * a.vx - 1) / (64 * a.vx);
+            a.tiles_z = (a.nz + a.zc - 1) / a.zc;
+            if ((int64_t)a.tiles_x * a.tiles_z >= 2048) break;
+        }
         a.tiles_y = 1;
-        a.tiles_z = (a.nz + a.zc - 1) / a.zc;
     } else {
         const int VX = storage == kF32 ? k3dVX32 : k3dVX16;
         const int RY = storage == kF32 ? k3dRY32 : k3dRY16;
         const int NW = storage == kF32 ? FD_3D_NW32 : FD_3D_NW16;
         const int TX = 64 * VX, TY = NW * RY;
+        a.vx = VX;
         a.zc = FD_3D_ZC;
         a.tiles_x = (a.nx + TX - 1) / TX;
         a.tiles_y = (a.ny + TY - 1) / TY;
@@ -725,21 +727,28 @@ static void launch3d(const StepArgs &a, int nb, hipStream_t s)
                            dim3(64 * FD_3D_NW16), 0, s, a);
 }
 
+template <int VX>
+static void launch2d(const StepArgs &a, int storage, int mode, int nb, hipStream_t s)
+{
+    const dim3 g(nb), b(64);
+    if (storage == kF32) {
+        if (mode == kFwd) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwd>), g, b, 0, s, a);
+        else if (mode == kFwdLap) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwdLap>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_step2d<kF32, VX, kAdj>), g, b, 0, s, a);
+    } else if (storage == kF16) {
+        hipLaunchKernelGGL((k_step2d<kF16, VX, kFwd>), g, b, 0, s, a);
+    } else {
+        hipLaunchKernelGGL((k_step2d<kBF16, VX, kFwd>), g, b, 0, s, a);
+    }
+}
+
 hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t s)
 {
-    plan_tiles(a, ndim, storage);
+    plan_tiles(a, ndim, storage, false);
     const int nb = a.tiles_x * a.tiles_y * a.tiles_z;
     if (ndim == 2) {
-        const dim3 g(nb), b(64);
-        if (storage == kF32) {
-            if (mode == kFwd) hipLaunchKernelGGL((k_step2d<kF32, k2dVX, kFwd>), g, b, 0, s, a);
-            else if (mode == kFwdLap) hipLaunchKernelGGL((k_step2d<kF32, k2dVX, kFwdLap>), g, b, 0, s, a);
-            else hipLaunchKernelGGL((k_step2d<kF32, k2dVX, kAdj>), g, b, 0, s, a);
-        } else if (storage == kF16) {
-            hipLaunchKernelGGL((k_step2d<kF16, k2dVX, kFwd>), g, b, 0, s, a);
-        } else {
-            hipLaunchKernelGGL((k_step2d<kBF16, k2dVX, kFwd>), g, b, 0, s, a);
-        }
+        if (a.vx == 2) launch2d<2>(a, storage, mode, nb, s);
+        else launch2d<1>(a, storage, mode, nb, s);
     } else {
         if (storage == kF32) {
             if (mode == kFwd) launch3d<kF32, kFwd>(a, nb, s);
@@ -758,13 +767,13 @@ hipError_t launch_step_batch2d(Batch2D &b, hipStream_t s)
 {
     int total = 0;
     for (int i = 0; i < b.count; ++i) {
-        plan_tiles(b.it[i], 2, kF32);
+        plan_tiles(b.it[i], 2, kF32, true);
         b.begin[i] = total;
         total += b.it[i].tiles_x * b.it[i].tiles_z;
     }
     b.begin[b.count] = total;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_step2d_batch<k2dVX>), dim3(total), dim3(64), 0, s, b);
+    hipLaunchKernelGGL((k_step2d_batch<kBatchVX>), dim3(total), dim3(64), 0, s, b);
     return hipGetLastError();
 }
 

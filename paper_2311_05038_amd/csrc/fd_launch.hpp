@@ -18,8 +18,9 @@ struct Batch2D {
 };
 static_assert(sizeof(Batch2D) <= 4096, "batched step arguments must fit the kernel-argument segment");
 
-// Fills tiles_x/y/z and zc of `a` for the kernel variant that runs it.
-void plan_tiles(StepArgs &a, int ndim, int storage);
+// Fills tiles_x/y/z, zc and vx of `a` for the kernel variant that runs it
+// (batched: the tile width of the batched 2D kernel).
+void plan_tiles(StepArgs &a, int ndim, int storage, bool batched);
 
 hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t s);
 hipError_t launch_step_batch2d(Batch2D &b, hipStream_t s);
