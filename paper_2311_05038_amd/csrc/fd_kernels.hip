@@ -138,62 +138,51 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
     const bool hlane = (lane < 4) || (lane >= 60);
     const bool hvalid = hx >= 0 && hx < nx;
 
-    auto ld_cur = [&](int z, float (&o)[VX]) {
-        if (z >= 0 && z < nz && lane_in) {
-            const Pack<T, VX> p = ldp<T, VX>(cur + (size_t)z * px + x0);
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = decode<ST>(p.v[v], h.sc);
-        } else {
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
-        }
+    // Loads return raw packs (zero outside the grid); values are decoded
+    // where they are consumed, so a prefetch never waits for its own load.
+    using PT = Pack<T, VX>;
+    using PF = Pack<float, VX>;
+    auto ld_cur = [&](int z) -> PT {
+        PT p{};
+        if (z >= 0 && z < nz && lane_in) p = ldp<T, VX>(cur + (size_t)z * px + x0);
+        return p;
     };
-    auto ld_prev = [&](int z, float (&o)[VX]) {
-        if (z < nz && lane_in) {
-            const Pack<T, VX> p = ldp<T, VX>(prv + (size_t)z * px + x0);
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = decode<ST>(p.v[v], h.sp);
-        } else {
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
-        }
+    auto ld_prev = [&](int z) -> PT {
+        PT p{};
+        if (z < nz && lane_in) p = ldp<T, VX>(prv + (size_t)z * px + x0);
+        return p;
     };
-    auto ld_c = [&](int z, float (&o)[VX]) {
-        if (z < nz && lane_in) {
-            const Pack<float, VX> p = ldp<float, VX>(a.c + (size_t)z * px + x0);
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = p.v[v];
-        } else {
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
-        }
+    auto ld_c = [&](int z) -> PF {
+        PF p{};
+        if (z < nz && lane_in) p = ldp<float, VX>(a.c + (size_t)z * px + x0);
+        return p;
     };
-    auto ld_halo = [&](int z) -> float {
-        return (hvalid && z < nz) ? decode<ST>(cur[(size_t)z * px + hx], h.sc) : 0.0f;
-    };
+    auto ld_halo = [&](int z) -> T { return (hvalid && z < nz) ? cur[(size_t)z * px + hx] : (T)0; };
 
     float q[9][VX];
 #pragma unroll
-    for (int k = 0; k < 8; ++k) ld_cur(zb - 4 + k, q[k]);
-    float la[VX], pv[VX], cv[VX];
-    ld_cur(zb + 4, la);
-    ld_prev(zb, pv);
-    ld_c(zb, cv);
-    float hv = ld_halo(zb);
+    for (int k = 0; k < 8; ++k) {
+        const PT p = ld_cur(zb - 4 + k);
+#pragma unroll
+        for (int v = 0; v < VX; ++v) q[k][v] = decode<ST>(p.v[v], h.sc);
+    }
+    PT la = ld_cur(zb + 4), pv = ld_prev(zb);
+    PF cv = ld_c(zb);
+    T hv = ld_halo(zb);
 
     for (int z = zb; z < ze; ++z) {
         float pc[VX], cc[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
-            q[8][v] = la[v];
-            pc[v] = pv[v];
-            cc[v] = cv[v];
+            q[8][v] = decode<ST>(la.v[v], h.sc);
+            pc[v] = decode<ST>(pv.v[v], h.sp);
+            cc[v] = cv.v[v];
         }
-        const float hc = hv;
+        const float hc = decode<ST>(hv, h.sc);
         if (z + 1 < ze) {
-            ld_cur(z + 5, la);
-            ld_prev(z + 1, pv);
-            ld_c(z + 1, cv);
+            la = ld_cur(z + 5);
+            pv = ld_prev(z + 1);
+            cv = ld_c(z + 1);
             hv = ld_halo(z + 1);
         }
         float *rw = row[z & 1];
@@ -323,66 +312,57 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
     }
     const bool hxv = hxl && hxx >= 0 && hxx < nx && hxy < ny;
 
-    auto ld3 = [&](const T *base, int z, int y, float s, float (&o)[VX]) {
-        if (z >= 0 && z < nz && y < ny && lane_in) {
-            const Pack<T, VX> p = ldp<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = decode<ST>(p.v[v], s);
-        } else {
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
-        }
+    // Loads return raw packs (zero outside the grid); values are decoded
+    // where they are consumed, so a prefetch never waits for its own load.
+    using PT = Pack<T, VX>;
+    using PF = Pack<float, VX>;
+    auto ld3 = [&](const T *base, int z, int y) -> PT {
+        PT p{};
+        if (z >= 0 && z < nz && y < ny && lane_in)
+            p = ldp<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
+        return p;
     };
-    auto ld3nt = [&](const T *base, int z, int y, float s, float (&o)[VX]) {
-        if (z < nz && y < ny && lane_in) {
-            const Pack<T, VX> p = ldp_stream<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = decode<ST>(p.v[v], s);
-        } else {
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
-        }
+    auto ld3nt = [&](const T *base, int z, int y) -> PT {
+        PT p{};
+        if (z < nz && y < ny && lane_in)
+            p = ldp_stream<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
+        return p;
     };
-    auto ldc3 = [&](int z, int y, float (&o)[VX]) {
-        if (z < nz && y < ny && lane_in) {
-            const Pack<float, VX> p = ldp_stream<float, VX>(a.c + (size_t)z * pp + (size_t)y * px + x0);
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = p.v[v];
-        } else {
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
-        }
+    auto ldc3 = [&](int z, int y) -> PF {
+        PF p{};
+        if (z < nz && y < ny && lane_in)
+            p = ldp_stream<float, VX>(a.c + (size_t)z * pp + (size_t)y * px + x0);
+        return p;
     };
-    auto ldhy = [&](int z, int hh, float (&o)[VX]) {
-        if (hyv[hh] && z < nz) {
-            const Pack<T, VX> p = ldp<T, VX>(cur + (size_t)z * pp + (size_t)hy[hh] * px + x0);
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = decode<ST>(p.v[v], h.sc);
-        } else {
-#pragma unroll
-            for (int v = 0; v < VX; ++v) o[v] = 0.0f;
-        }
+    auto ldhy = [&](int z, int hh) -> PT {
+        PT p{};
+        if (hyv[hh] && z < nz) p = ldp<T, VX>(cur + (size_t)z * pp + (size_t)hy[hh] * px + x0);
+        return p;
     };
-    auto ldhx = [&](int z) -> float {
-        return (hxv && z < nz) ? decode<ST>(cur[(size_t)z * pp + (size_t)hxy * px + hxx], h.sc)
-                               : 0.0f;
+    auto ldhx = [&](int z) -> T {
+        return (hxv && z < nz) ? cur[(size_t)z * pp + (size_t)hxy * px + hxx] : (T)0;
     };
 
     float q[RY][9][VX];
 #pragma unroll
     for (int j = 0; j < RY; ++j)
 #pragma unroll
-        for (int k = 0; k < 8; ++k) ld3(cur, zb - 4 + k, yj[j], h.sc, q[j][k]);
-    float la[RY][VX], pv[RY][VX], cv[RY][VX], yh[HH][VX];
+        for (int k = 0; k < 8; ++k) {
+            const PT p = ld3(cur, zb - 4 + k, yj[j]);
+#pragma unroll
+            for (int v = 0; v < VX; ++v) q[j][k][v] = decode<ST>(p.v[v], h.sc);
+        }
+    PT la[RY], pv[RY], yh[HH];
+    PF cv[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-        ld3(cur, zb + 4, yj[j], h.sc, la[j]);
-        ld3nt(prv, zb, yj[j], h.sp, pv[j]);
-        ldc3(zb, yj[j], cv[j]);
+        la[j] = ld3(cur, zb + 4, yj[j]);
+        pv[j] = ld3nt(prv, zb, yj[j]);
+        cv[j] = ldc3(zb, yj[j]);
     }
 #pragma unroll
-    for (int hh = 0; hh < HH; ++hh) ldhy(zb, hh, yh[hh]);
-    float xh = ldhx(zb);
+    for (int hh = 0; hh < HH; ++hh) yh[hh] = ldhy(zb, hh);
+    T xh = ldhx(zb);
     float bmax = 0.0f;
 
     for (int z = zb; z < ze; ++z) {
@@ -391,24 +371,24 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
         for (int j = 0; j < RY; ++j)
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
-                q[j][8][v] = la[j][v];
-                pc[j][v] = pv[j][v];
-                cc[j][v] = cv[j][v];
+                q[j][8][v] = decode<ST>(la[j].v[v], h.sc);
+                pc[j][v] = decode<ST>(pv[j].v[v], h.sp);
+                cc[j][v] = cv[j].v[v];
             }
 #pragma unroll
         for (int hh = 0; hh < HH; ++hh)
 #pragma unroll
-            for (int v = 0; v < VX; ++v) yhc[hh][v] = yh[hh][v];
-        const float xhc = xh;
+            for (int v = 0; v < VX; ++v) yhc[hh][v] = decode<ST>(yh[hh].v[v], h.sc);
+        const float xhc = decode<ST>(xh, h.sc);
         if (z + 1 < ze) {
 #pragma unroll
             for (int j = 0; j < RY; ++j) {
-                ld3(cur, z + 5, yj[j], h.sc, la[j]);
-                ld3nt(prv, z + 1, yj[j], h.sp, pv[j]);
-                ldc3(z + 1, yj[j], cv[j]);
+                la[j] = ld3(cur, z + 5, yj[j]);
+                pv[j] = ld3nt(prv, z + 1, yj[j]);
+                cv[j] = ldc3(z + 1, yj[j]);
             }
 #pragma unroll
-            for (int hh = 0; hh < HH; ++hh) ldhy(z + 1, hh, yh[hh]);
+            for (int hh = 0; hh < HH; ++hh) yh[hh] = ldhy(z + 1, hh);
             xh = ldhx(z + 1);
         }
         float *P = pl[z & 1];
@@ -695,9 +675,9 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
     if (ndim == 2) {
         static const int cand[4][2] = {{2, 16}, {2, 8}, {1, 8}, {1, 4}};
         for (int i = 0; i < 4; ++i) {
+            if (batched && cand[i][0] != kBatchVX) continue;  // the batched kernel's width only
             a.vx = cand[i][0];
             a.zc = cand[i][1];
-            if (batched && a.vx != kBatchVX) continue;
             a.tiles_x = (a.nx + 64 * a.vx - 1) / (64 * a.vx);
             a.tiles_z = (a.nz + a.zc - 1) / a.zc;
             if ((int64_t)a.tiles_x * a.tiles_z >= 2048) break;
