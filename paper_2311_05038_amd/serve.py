@@ -1,0 +1,237 @@
+"""Shot server: continuous batching of forward-modelling requests.
+
+Requests (one shot each, on its own 2D grid and velocity model) arrive over
+time.  The scheduler admits a waiting request as soon as a batch slot is free
+and its device footprint fits the HBM budget, starts it (model set-up and
+first source addition), and advances every admitted shot with ONE batched
+kernel launch per time step (``fd_step_batch``), so that work of shots that
+arrived at different times overlaps on the device.  A shot leaves the batch
+after its last step; its memory returns to the budget once the device has
+passed that step.  Latency = completion - arrival.
+
+The scheduling core (`Scheduler`) is device-agnostic: it drives any object
+with the methods of `TorchDevice` (footprint, start, advance, fence, done,
+wait, elapsed, finish), which lets the policy be tested on the CPU against a
+simulated device.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import time
+from typing import Any, Callable, Dict, List, Optional
+
+import torch
+
+
+@dataclasses.dataclass
+class Request:
+    rid: int
+    arrival: float          # seconds after the stream starts
+    nz: int
+    nx: int
+    nt: int
+    payload: Any = None     # device-specific inputs (grid, velocity, shot ...)
+
+
+@dataclasses.dataclass
+class Outcome:
+    rid: int
+    arrival: float
+    admitted: float = float("nan")
+    finished: float = float("nan")
+    status: str = "pending"     # "ok" or "failed: ..."
+    result: Any = None
+
+    @property
+    def latency(self) -> float:
+        return self.finished - self.arrival
+
+
+class Scheduler:
+    """Admission by free slots and HBM bytes, FIFO order, batched stepping in
+    chunks of `chunk` steps with at most `depth` chunks queued on the device.
+
+    Time comes from device.elapsed() (device clock since the stream start)."""
+
+    def __init__(self, device, max_slots: int = 16, hbm_budget: int = 64 << 30,
+                 chunk: int = 25, depth: int = 2):
+        self.dev = device
+        self.max_slots = max_slots
+        self.budget = hbm_budget
+        self.chunk = chunk
+        self.depth = depth
+        self.peak_bytes = 0
+        self.peak_slots = 0
+        self.launch_steps = 0
+
+    def run(self, requests: List[Request]) -> Dict[int, Outcome]:
+        dev = self.dev
+        pending = collections.deque(sorted(requests, key=lambda r: r.arrival))
+        waiting: collections.deque = collections.deque()
+        active: List[Any] = []          # device handles in the batch
+        owner: Dict[int, Request] = {}  # id(handle) -> request
+        inflight: collections.deque = collections.deque()  # (token, [handles done])
+        used = 0
+        out = {r.rid: Outcome(r.rid, r.arrival) for r in requests}
+        dev.begin_stream()
+        while pending or waiting or active or inflight:
+            now = dev.elapsed()
+            while pending and pending[0].arrival <= now:
+                waiting.append(pending.popleft())
+            # admission, FIFO: the head waits until it fits
+            while waiting and len(active) < self.max_slots:
+                req = waiting[0]
+                fp = dev.footprint(req)
+                if used + fp > self.budget:
+                    if not active and not inflight and fp > self.budget:
+                        waiting.popleft()
+                        out[req.rid].status = "failed: footprint exceeds the HBM budget"
+                        continue
+                    break
+                waiting.popleft()
+                try:
+                    h = dev.start(req)
+                except Exception as e:  # a bad request fails alone
+                    out[req.rid].status = f"failed: {e}"
+                    out[req.rid].finished = dev.elapsed()
+                    continue
+                used += fp
+                owner[id(h)] = req
+                out[req.rid].admitted = dev.elapsed()
+                active.append(h)
+            self.peak_bytes = max(self.peak_bytes, used)
+            self.peak_slots = max(self.peak_slots, len(active))
+            if active:
+                finished = dev.advance(active, self.chunk)
+                self.launch_steps += self.chunk
+                inflight.append((dev.fence(), finished))
+                done_ids = {id(h) for h in finished}
+                active = [h for h in active if id(h) not in done_ids]
+            # Retire completed chunks.  Block on the oldest chunk when too many
+            # are queued, or when nothing is left to enqueue (its retirement
+            # is what frees slots and memory for the waiting requests).
+            while inflight and (len(inflight) > self.depth or not active or
+                                dev.done(inflight[0][0])):
+                token, finished = inflight.popleft()
+                dev.wait(token)
+                t_done = dev.token_time(token)
+                for h in finished:
+                    req = owner.pop(id(h))
+                    o = out[req.rid]
+                    o.finished = t_done
+                    o.status = "ok"
+                    o.result = dev.finish(h)
+                    used -= dev.footprint(req)
+                if not active and waiting:
+                    break   # go back and admit
+            if not active and not inflight and not waiting and pending:
+                dev.idle_until(pending[0].arrival)
+        return out
+
+
+def summarize(outcomes: Dict[int, Outcome], cell_updates: Callable[[int], float]) -> dict:
+    """shots/s, p50/p99 latency and Gcell-updates/s over the successful shots."""
+    ok = [o for o in outcomes.values() if o.status == "ok"]
+    if not ok:
+        return dict(shots=0)
+    lat = sorted(o.latency for o in ok)
+    t_end = max(o.finished for o in ok)
+    t_first = min(o.arrival for o in ok)
+    q = lambda p: lat[min(len(lat) - 1, int(round(p * (len(lat) - 1))))]
+    work = sum(cell_updates(o.rid) for o in ok)
+    return dict(shots=len(ok), failed=len(outcomes) - len(ok),
+                makespan_s=t_end - t_first, shots_per_s=len(ok) / (t_end - t_first),
+                p50_latency_s=q(0.50), p99_latency_s=q(0.99), mean_latency_s=sum(lat) / len(lat),
+                gcell_per_s=work / (t_end - t_first) / 1e9)
+
+
+class TorchDevice:
+    """The GPU side of the scheduler: libfd.so through the Python binding.
+
+    `make_inputs(req)` returns (Grid, velocity tensor, Shot) for a request.
+    batched=True steps all admitted shots with fd_step_batch; batched=False
+    runs each shot alone with fd_run_shot (the plain sequential path; use it
+    with max_slots=1)."""
+
+    def __init__(self, make_inputs: Callable, batched: bool = True, keep_traces: bool = False):
+        from . import _abi
+        self._abi = _abi
+        self.make_inputs = make_inputs
+        self.batched = batched
+        self.keep_traces = keep_traces
+        self.stream = torch.cuda.current_stream()
+        self.side = torch.cuda.Stream()
+        self._fp: Dict[int, int] = {}
+        self.t0_event = None
+        self.t0_wall = 0.0
+
+    # clock: device time since begin_stream, in seconds
+    def begin_stream(self):
+        torch.cuda.synchronize()
+        self.t0_event = torch.cuda.Event(enable_timing=True)
+        self.t0_event.record(self.stream)
+        self.t0_wall = time.perf_counter()
+
+    def elapsed(self) -> float:
+        return time.perf_counter() - self.t0_wall
+
+    def idle_until(self, t: float):
+        while self.elapsed() < t:
+            time.sleep(min(1e-3, max(0.0, t - self.elapsed())))
+
+    def footprint(self, req: Request) -> int:
+        if req.rid not in self._fp:
+            from . import Grid
+            g = Grid(ndim=2, nz=req.nz, ny=1, nx=req.nx, dh=10.0, dt=1e-3)
+            s = self._abi.fd_query_bytes(g.c())
+            nrec = req.nx
+            self._fp[req.rid] = int(s.model + s.state + req.nt * nrec * 4 + req.nz * req.nx * 4)
+        return self._fp[req.rid]
+
+    def start(self, req: Request):
+        from . import Model
+        # Inputs and model set-up on the side stream: fd_create_model waits
+        # for the side stream only, never for the batch queued on the main
+        # stream.  Side-stream memory used later by the main stream is
+        # recorded on it so the allocator does not hand it out early.
+        with torch.cuda.stream(self.side):
+            grid, velocity, shot = self.make_inputs(req)
+            model = Model(grid, velocity, stream=self.side)
+        model.buf.record_stream(self.stream)
+        shot.wavelet.record_stream(self.stream)
+        state = model.new_state()
+        traces = torch.empty((shot.nt, max(shot.nrec, 1)), dtype=torch.float32,
+                             device=velocity.device)
+        h = dict(model=model, state=state, shot=shot, traces=traces, req=req)
+        if self.batched:
+            state.begin(shot, stream=self.stream)
+        return h
+
+    def advance(self, handles, nsteps: int):
+        from . import step_batch
+        if self.batched:
+            entries = [(h["model"], h["state"], h["shot"], h["traces"]) for h in handles]
+            for i in range(0, len(entries), self._abi.FD_BATCH_MAX):
+                step_batch(entries[i:i + self._abi.FD_BATCH_MAX], nsteps, stream=self.stream)
+            return [h for h in handles if h["state"].next >= h["shot"].nt]
+        for h in handles:   # plain path: the whole shot in one call
+            h["model"].run_shot(h["state"], h["shot"], h["traces"], stream=self.stream)
+        return list(handles)
+
+    def fence(self):
+        ev = torch.cuda.Event(enable_timing=True)
+        ev.record(self.stream)
+        return ev
+
+    def done(self, token) -> bool:
+        return token.query()
+
+    def wait(self, token):
+        token.synchronize()
+
+    def token_time(self, token) -> float:
+        return self.t0_event.elapsed_time(token) * 1e-3
+
+    def finish(self, h):
+        return h["traces"] if self.keep_traces else None
