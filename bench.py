@@ -9,7 +9,11 @@ block at depth index 2, FP32 fields.  One benchmark step = one whole shot
 Prints ONE JSON line with Mcell-updates/s, the roofline of the dominant
 kernel (the 3D step kernel: 16 algorithmic bytes per cell-update in FP32 -
 read P, Pold and c, write Pnew) and the FP64 CPU oracle timed on a bounded
-sample of the same workload.
+sample of the same workload.  Further legs (each against the plain FP32 path
+on the same GPU) add keys to the same line:
+  half     16-bit field storage on the 768x768x512 precision grid, 2000 steps
+  adjoint  the 8-shot velocity gradient on the 1024^2 model, 2000 steps
+  serve    a Poisson stream of 2D shots, continuous batching vs sequential
 """
 from __future__ import annotations
 
@@ -87,7 +91,131 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 20):
     return dict(bytes_per_copy=2 * nbytes, gbs=2 * nbytes * reps / (ms * 1e-3) / 1e9)
 
 
-def cpu_baseline(nsteps: int = 4):
+def half_leg(nt: int = 2000):
+    """16-bit storage vs FP32 on the 768x768x512 grid (same model, source,
+    receivers): Mcell-updates/s of one whole shot each."""
+    import torch
+    import fd_inputs as fi
+    from helpers import setup
+    p = fi.precision3d(nt=nt)
+    v = p.velocity()
+    out = {}
+    for name, st in (("f32", 0), ("f16", 1), ("bf16", 2)):
+        model, state, shot = setup(p, v, storage=st)
+        traces = torch.empty((p.nt, p.receivers.count), device="cuda")
+        model.run_shot(state, shot, traces)     # warm-up shot
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        model.run_shot(state, shot, traces)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1)
+        bpc = 16 if st == 0 else 10
+        out[name] = dict(mcell_per_s=round(p.ncells * p.nt / (ms * 1e-3) / 1e6, 1),
+                         ms_per_shot=round(ms, 2),
+                         alg_gbs=round(bpc * p.ncells * p.nt / (ms * 1e-3) / 1e9, 1))
+        log(f"[bench] half leg {name}: {out[name]}")
+        del model, state, shot, traces
+        torch.cuda.empty_cache()
+    out["speedup_f16"] = round(out["f16"]["mcell_per_s"] / out["f32"]["mcell_per_s"], 3)
+    out["speedup_bf16"] = round(out["bf16"]["mcell_per_s"] / out["f32"]["mcell_per_s"], 3)
+    out["workload"] = "precision3d 768x768x512, nt=2000"
+    return out
+
+
+def adjoint_leg(nt: int = 2000, every: int = 50):
+    """The 8-shot L2-misfit gradient on the 1024^2 model: forward with
+    checkpoints, then recompute + adjoint per shot (FP64 time sum)."""
+    import torch
+    import fd_inputs as fi
+    from helpers import receivers_of
+    import paper_2311_05038_amd as fd
+    from paper_2311_05038_amd.autograd import l2_misfit_gradient
+    shots_p, vtrue, v0 = fi.adjoint2d(nt=nt)
+    p = shots_p[0]
+    grid = fd.Grid(ndim=2, nz=p.nz, ny=1, nx=p.nx, dh=p.dh, dt=p.dt,
+                   sponge_width=p.sponge_width, sponge_faces=p.sponge_faces)
+    wav = torch.from_numpy(p.wavelet()).cuda()
+    shots = [fd.Shot(q.src, wav, receivers_of(q)) for q in shots_p]
+    vt = torch.from_numpy(vtrue.ravel()).cuda()
+    mt = fd.Model(grid, vt)
+    st = mt.new_state()
+    obs = torch.stack([mt.run_shot(st, s).clone() for s in shots])
+    v0t = torch.from_numpy(v0.ravel()).cuda()
+    l2_misfit_gradient(v0t, grid, shots[:1], obs[:1], every)     # warm-up
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    J, g = l2_misfit_gradient(v0t, grid, shots, obs, every)
+    torch.cuda.synchronize()
+    sec = time.perf_counter() - t
+    cells = p.ncells * p.nt * len(shots)
+    out = dict(workload="adjoint2d 1024^2, 8 shots, nt=2000, K=50", seconds_per_gradient=round(sec, 3),
+               forward_equiv_mcell_per_s=round(3 * cells / sec / 1e6, 1), misfit=J,
+               grad_norm=float(g.norm()))
+    log(f"[bench] adjoint leg: {out}")
+    return out
+
+
+def serve_leg(n_requests: int = 60, seed: int = 50):
+    """A Poisson stream (50 shots/s) of 2D shots on grids drawn from
+    512^2..2048x4096: continuous batching vs sequential plain FP32 runs."""
+    import numpy as np
+    import torch
+    import fd_inputs as fi
+    import paper_2311_05038_amd as fd
+    from paper_2311_05038_amd.serve import Request, Scheduler, TorchDevice, summarize
+    reqs_in = fi.serving_stream(n_requests, seed=seed)
+    K = 4
+    base = [torch.from_numpy(fi.grf_velocity((2048, 4096), seed * 100 + k)).cuda() for k in range(K)]
+    wav_all = torch.from_numpy(fi.ricker(10.0, 1e-3, 4000)).cuda()
+
+    def make_inputs(req):
+        p = fi.surface2d(req.nz, req.nx, req.nt, req.rid)
+        g = fd.Grid(ndim=2, nz=p.nz, ny=1, nx=p.nx, dh=p.dh, dt=p.dt,
+                    sponge_width=p.sponge_width, sponge_faces=p.sponge_faces)
+        v = base[req.rid % K][: p.nz, : p.nx].contiguous().reshape(-1)
+        r = p.receivers
+        shot = fd.Shot(p.src, wav_all[: p.nt], fd.Receivers(r.z0, r.y0, r.x0, r.nz, r.ny, r.nx))
+        return g, v, shot
+
+    reqs = [Request(r.rid, r.arrival, r.nz, r.nx, r.nt) for r in reqs_in]
+    cells = {r.rid: r.nz * r.nx * r.nt for r in reqs}
+    res = {}
+    for name, batched, slots in (("batched", True, 16), ("sequential", False, 1)):
+        torch.cuda.synchronize()
+        sch = Scheduler(TorchDevice(make_inputs, batched=batched), max_slots=slots,
+                        hbm_budget=200 << 30, chunk=25)
+        out = sch.run(reqs)
+        res[name] = {k: (round(v, 4) if isinstance(v, float) else v)
+                     for k, v in summarize(out, cells.get).items()}
+        res[name]["peak_slots"] = sch.peak_slots
+        log(f"[bench] serve {name}: {res[name]}")
+    offered = sum(cells.values()) / (reqs[-1].arrival - reqs[0].arrival)
+    res["offered_gcell_per_s"] = round(offered / 1e9, 1)
+    res["workload"] = f"serving stream: {n_requests} Poisson shots at 50/s, 512^2..2048x4096, nt 1000..4000"
+    return res
+
+
+def traffic_from_profiles(kernel_tag: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, or
+    None when the kernel source changed after the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"{kernel_tag}_traffic.json")
+    if not os.path.exists(path):
+        return None
+    rec = json.load(open(path))
+    src = os.path.join(ROOT, "paper_2311_05038_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(src)):
+        h.update(open(os.path.join(src, f), "rb").read())
+    if rec.get("source_sha256") != h.hexdigest():
+        return None
+    return rec["bytes_per_launch"]
+
+
+def cpu_baseline(nsteps: int = 16):
     """The FP64 oracle on the same 512^3 model for a few steps."""
     import oracle
     import fd_inputs as fi
@@ -113,6 +241,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--probe-only", action="store_true",
                     help="only the 1 GiB copy probe (counter calibration)")
+    ap.add_argument("--legs", default="half,adjoint,serve",
+                    help="comma list of extra legs (half, adjoint, serve) or 'none'")
+    ap.add_argument("--serve-requests", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this engine runs on one GPU; --gpus {args.gpus} is not supported "
@@ -131,7 +262,16 @@ def main():
         print(json.dumps({"copy_probe": probe}), flush=True)
         return
     h = headline(args.steps, args.warmup)
+    legs = [x for x in args.legs.split(",") if x and x != "none"]
+    extra = {}
+    if "half" in legs:
+        extra["half_storage"] = half_leg()
+    if "adjoint" in legs:
+        extra["adjoint"] = adjoint_leg()
+    if "serve" in legs:
+        extra["serving"] = serve_leg(args.serve_requests)
     cpu = None if args.no_cpu else cpu_baseline()
+    traffic = traffic_from_profiles("k_step3d_f32_layered3d_512")
     out = {
         "metric": "Mcell-updates/s",
         "value": round(h["mcell"], 1),
@@ -150,11 +290,12 @@ def main():
         "hbm_frac": round(h["achieved"] / HBM_PEAK_GBS, 4),
         "roofline": {"bound": "hbm", "achieved": round(h["achieved"], 1), "peak": HBM_PEAK_GBS,
                      "unit": "GB/s", "frac": round(h["achieved"] / HBM_PEAK_GBS, 4),
-                     "traffic": None, "kernel": "k_step3d<f32>",
+                     "traffic": traffic, "kernel": "k_step3d<f32>",
                      "bytes_per_cell": 16, "avg_launch_us": round(h["per_launch_us"], 2)},
         "cpu_baseline": cpu,
         "copy_roof_gbs": round(probe["gbs"], 1),
     }
+    out.update(extra)
     print(json.dumps(out), flush=True)
 
 
