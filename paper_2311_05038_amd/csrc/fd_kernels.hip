@@ -11,6 +11,8 @@
 //   a double-buffered LDS copy of the current plane with a 4-cell halo.
 // Both follow the fused step of arXiv 2311.05038, Section 7 (Listing 3's
 // add_source, fd_pzz, fd_pxx, fd_time and swap in one pass).
+#include <algorithm>
+
 #include "fd_device.hpp"
 #include "fd_launch.hpp"
 
@@ -658,12 +660,39 @@ hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, i
 #ifndef FD_3D_NW16
 #define FD_3D_NW16 4
 #endif
-#ifndef FD_3D_ZC
-#define FD_3D_ZC 64
-#endif
 constexpr int k3dVX32 = FD_3D_VX32, k3dRY32 = FD_3D_RY32;   // FP32 fields
 constexpr int k3dVX16 = FD_3D_VX16, k3dRY16 = FD_3D_RY16;   // 16-bit fields
 constexpr int kBatchVX = 2;
+
+// Blocks of the 3D forward kernel that fit on the device at once (queried
+// once per storage kind; the CU count times the occupancy per CU).
+static int64_t resident_blocks_3d(int storage)
+{
+    static int64_t cache[3] = {0, 0, 0};
+    const int k = storage == kF32 ? 0 : (storage == kF16 ? 1 : 2);
+    if (cache[k] == 0) {
+        int dev = 0, cus = 0, per_cu = 0;
+        hipError_t e = hipGetDevice(&dev);
+        if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+        if (e == hipSuccess) {
+            if (storage == kF32)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF32, k3dVX32, k3dRY32, FD_3D_NW32, kFwd>),
+                    64 * FD_3D_NW32, 0);
+            else if (storage == kF16)
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd>),
+                    64 * FD_3D_NW16, 0);
+            else
+                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kBF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd>),
+                    64 * FD_3D_NW16, 0);
+        }
+        (void)hipGetLastError();
+        cache[k] = (e == hipSuccess && cus > 0 && per_cu > 0) ? (int64_t)cus * per_cu : 512;
+    }
+    return cache[k];
+}
 
 // Tile shapes.  3D: NW waves, (64 VX) x (NW RY) cells by zc planes (the
 // defaults come from a sweep of shapes on the 512^3 and 768x768x512 grids).
@@ -689,9 +718,27 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
         const int NW = storage == kF32 ? FD_3D_NW32 : FD_3D_NW16;
         const int TX = 64 * VX, TY = NW * RY;
         a.vx = VX;
-        a.zc = FD_3D_ZC;
         a.tiles_x = (a.nx + TX - 1) / TX;
         a.tiles_y = (a.ny + TY - 1) / TY;
+#ifdef FD_3D_ZC_FIXED
+        a.zc = FD_3D_ZC_FIXED;
+#else
+        // Planes per block: a block streams zc planes after priming 8 halo
+        // planes, and blocks run in ceil(blocks / resident) rounds, so the
+        // time goes as ceil(blocks / resident) * (zc + 8).  Ties go to the
+        // longer chunk (less halo traffic).
+        const int64_t cols = (int64_t)a.tiles_x * a.tiles_y;
+        const int64_t resident = resident_blocks_3d(storage);
+        int64_t best = -1;
+        for (int zc = 256; zc >= 16; zc >>= 1) {
+            const int64_t nb = cols * ((a.nz + zc - 1) / zc);
+            const int64_t cost = ((nb + resident - 1) / resident) * (std::min(zc, a.nz) + 8);
+            if (best < 0 || cost < best) {
+                best = cost;
+                a.zc = zc;
+            }
+        }
+#endif
         a.tiles_z = (a.nz + a.zc - 1) / a.zc;
     }
 }

@@ -49,9 +49,22 @@ def make(name: str) -> str:
     p = {"layered3d_512": fi.layered3d(), "precision3d_768": fi.precision3d()}[name]
     t0 = time.time()
     v = p.velocity()
-    out = oracle.forward(oracle.grid_of(p), v, p.wavelet(), p.nt, p.src, p.rec_index())
+    g = oracle.grid_of(p)
+    w = p.wavelet()
+    rec = p.rec_index()
+    traces = np.empty((p.nt, rec.size))
+    prev = cur = None
+    chunk = 50
+    # Continuing from the previous chunk's (prev, cur) with the wavelet slice
+    # of the next steps is the same arithmetic as one long run.
+    for n0 in range(0, p.nt, chunk):
+        k = min(chunk, p.nt - n0)
+        out = oracle.forward(g, v, w[n0:n0 + k], k, p.src, rec, init_prev=prev, init_cur=cur)
+        traces[n0:n0 + k] = out["traces"]
+        prev, cur = out["prev"], out["cur"]
+        print(f"{name}: step {n0 + k}/{p.nt} after {time.time() - t0:.0f} s", flush=True)
+    out = dict(traces=traces)
     traces_idx, cells_idx = sample_plan(p)
-    cur = out["cur"]
     path = os.path.join(HERE, f"{name}.npz")
     np.savez_compressed(
         path, traces_idx=traces_idx, traces=out["traces"][:, traces_idx],
