@@ -10,7 +10,11 @@ minutes (512^3) to hours (768x768x512), so the stored files hold samples:
   blocks                   : sums of the final field over 16^3 blocks
   trace_norm / field_norm  : L2 norms of the whole traces and final field
 
-Usage:  python tests/golden/make_golden.py layered3d_512 [precision3d_768]
+For adjoint2d_1024 (the 1024^2 / 2000-step gradient model, shot 0, start
+model v0, a seeded N(0,1) adjoint source r stored as FP32 in the file) the
+FP64 velocity gradient is stored the same way (cells, 16^2 block sums, norm).
+
+Usage:  python tests/golden/make_golden.py layered3d_512 [precision3d_768] [adjoint2d_1024]
 """
 from __future__ import annotations
 
@@ -45,7 +49,32 @@ def block_sums(field: np.ndarray, b: int = 16) -> np.ndarray:
     return f.reshape(nz // b, b, ny // b, b, nx // b, b).sum(axis=(1, 3, 5))
 
 
+def adjoint_residual(p: fi.Problem) -> np.ndarray:
+    return np.random.default_rng(777).standard_normal((p.nt, p.receivers.count)).astype(np.float32)
+
+
+def make_adjoint(name: str) -> str:
+    t0 = time.time()
+    shots, _, v0 = fi.adjoint2d()
+    p = shots[0]
+    r = adjoint_residual(p)
+    gv, _ = oracle.adjoint(oracle.grid_of(p), v0.reshape(p.nz, 1, p.nx), p.wavelet(), p.nt,
+                           p.src, p.rec_index(), r.astype(np.float64))
+    g = gv.reshape(p.nz, p.nx)
+    rng = np.random.default_rng(4321)
+    cells_idx = rng.integers(0, p.ncells, 8192).astype(np.int64)
+    b = 16
+    blocks = g.reshape(p.nz // b, b, p.nx // b, b).sum(axis=(1, 3))
+    path = os.path.join(HERE, f"{name}.npz")
+    np.savez_compressed(path, cells_idx=cells_idx, cells=g.ravel()[cells_idx], blocks=blocks,
+                        grad_norm=np.linalg.norm(g), seconds=time.time() - t0)
+    print(name, "written in %.0f s" % (time.time() - t0), flush=True)
+    return path
+
+
 def make(name: str) -> str:
+    if name == "adjoint2d_1024":
+        return make_adjoint(name)
     p = {"layered3d_512": fi.layered3d(), "precision3d_768": fi.precision3d()}[name]
     t0 = time.time()
     v = p.velocity()

@@ -66,3 +66,27 @@ def test_gradient_accumulates():
     model.adjoint_gradient(shot, adj, ck, 10, g)
     torch.cuda.synchronize()
     assert torch.allclose(g, 2 * g1, rtol=1e-12, atol=0)
+
+
+def test_full_size_gradient_against_stored_oracle():
+    """The 1024^2 / 2000-step gradient model (shot 0, start model, K = 50 as
+    in the benchmark) against the FP64 oracle gradient stored by
+    tests/golden/make_golden.py for the same seeded adjoint source."""
+    import os
+    import sys
+    path = os.path.join(os.path.dirname(__file__), "golden", "adjoint2d_1024.npz")
+    if not os.path.exists(path):
+        pytest.skip("stored oracle gradient not generated")
+    sys.path.insert(0, os.path.join(os.path.dirname(__file__), "golden"))
+    from make_golden import adjoint_residual
+    gold = np.load(path)
+    shots, _, v0 = fi.adjoint2d()
+    p = shots[0]
+    g = _grad_gpu(p, v0, adjoint_residual(p), 50)
+    e_cells = rel_l2(g.ravel()[gold["cells_idx"]], gold["cells"])
+    b = 16
+    blocks = g.reshape(p.nz // b, b, p.nx // b, b).sum(axis=(1, 3))
+    e_blocks = rel_l2(blocks, gold["blocks"])
+    e_norm = abs(np.linalg.norm(g) / float(gold["grad_norm"]) - 1)
+    print("1024^2 gradient errors", e_cells, e_blocks, e_norm, flush=True)
+    assert max(e_cells, e_blocks, e_norm) <= 1e-3
