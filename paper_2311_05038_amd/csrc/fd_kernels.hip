@@ -148,12 +148,14 @@ __device__ __forceinline__ float leapfrog(float G, float ctr, float c, float lap
 // --------------------------------------------------------------------------
 // 2D
 // --------------------------------------------------------------------------
-template <int ST, int VX, int MODE>
-__device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
+template <int ST, int VX, int MODE, bool FULL>
+__device__ __forceinline__ void step2d_body(const StepArgs &a, int tx, int tz,
                                             float (*row)[64 * VX + 8], const HalfCtx &h,
                                             float inj, float &bmax)
 {
     using T = typename Stor<ST>::T;
+    using PT = Pack<T, VX>;
+    using PF = Pack<float, VX>;
     constexpr int TX = 64 * VX;
     const int lane = threadIdx.x & 63;
     const int xb = tx * TX;
@@ -163,13 +165,16 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
     const T *__restrict__ cur = (const T *)a.cur;
     const T *__restrict__ prv = (const T *)a.prev;
     const size_t px = (size_t)a.px;
-    const bool lane_in = x0 < a.px;
+    const bool lane_in = FULL || x0 < a.px;
+    const size_t xoff = lane_in ? (size_t)x0 : 0;
     const int nx = a.nx, nz = a.nz;
 
     float gxv[VX];
 #pragma unroll
-    for (int v = 0; v < VX; ++v) gxv[v] = (x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
+    for (int v = 0; v < VX; ++v) gxv[v] = (FULL || x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
 
+    // x-halo: lanes 0..3 take the 4 cells left of the tile, lanes 60..63 the
+    // 4 cells right of it; read at a clamped address, zeroed by select.
     int hx = -1, hslot = 0;
     if (lane < 4) {
         hx = xb - 4 + lane;
@@ -180,48 +185,58 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
     }
     const bool hlane = (lane < 4) || (lane >= 60);
     const bool hvalid = hx >= 0 && hx < nx;
+    const size_t hoff = hvalid ? (size_t)hx : 0;
 
-    // Loads return raw packs (zero outside the grid); values are decoded
-    // where they are consumed, so a prefetch never waits for its own load.
-    using PT = Pack<T, VX>;
-    using PF = Pack<float, VX>;
+    // Loads return raw packs (zero outside the grid); values are decoded,
+    // without their power-of-two scale, where they are consumed.
     auto ld_cur = [&](int z) -> PT {
         PT p{};
-        if (z >= 0 && z < nz && lane_in) p = ldp<T, VX>(cur + (size_t)z * px + x0);
+        if (z >= 0 && z < nz && lane_in) p = ldp<T, VX>(cur + (size_t)z * px + xoff);
         return p;
     };
     auto ld_prev = [&](int z) -> PT {
         PT p{};
-        if (z < nz && lane_in) p = ldp<T, VX>(prv + (size_t)z * px + x0);
+        if (z < nz && lane_in) p = ldp<T, VX>(prv + (size_t)z * px + xoff);
         return p;
     };
     auto ld_c = [&](int z) -> PF {
         PF p{};
-        if (z < nz && lane_in) p = ldp<float, VX>(a.c + (size_t)z * px + x0);
+        if (z < nz && lane_in) p = ldp<float, VX>(a.c + (size_t)z * px + xoff);
         return p;
     };
-    auto ld_halo = [&](int z) -> T { return (hvalid && z < nz) ? cur[(size_t)z * px + hx] : (T)0; };
+    auto ld_halo = [&](int z) -> T {
+        T v = (T)0;
+        if (hlane && z < nz) {
+            const T r = cur[(size_t)z * px + hoff];
+            v = hvalid ? r : (T)0;
+        }
+        return v;
+    };
 
     float q[9][VX];
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
         const PT p = ld_cur(zb - 4 + k);
 #pragma unroll
-        for (int v = 0; v < VX; ++v) q[k][v] = decode<ST>(p.v[v], h.sc);
+        for (int v = 0; v < VX; ++v) q[k][v] = decode<ST>(p.v[v], 1.0f);
     }
     PT la = ld_cur(zb + 4), pv = ld_prev(zb);
     PF cv = ld_c(zb);
     T hv = ld_halo(zb);
 
+    const bool has_rec = (MODE == kAdj ? a.resid_row != nullptr : a.trace_row != nullptr) &&
+                         a.rec.nz > 0;
+    const int rz_last = a.rec.z0 + (a.rec.nz - 1) * a.rec.dz;
+
     for (int z = zb; z < ze; ++z) {
         float pc[VX], cc[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
-            q[8][v] = decode<ST>(la.v[v], h.sc);
-            pc[v] = decode<ST>(pv.v[v], h.sp);
+            q[8][v] = decode<ST>(la.v[v], 1.0f);
+            pc[v] = decode<ST>(pv.v[v], 1.0f);
             cc[v] = cv.v[v];
         }
-        const float hc = decode<ST>(hv, h.sc);
+        const float hc = decode<ST>(hv, 1.0f);
         if (z + 1 < ze) {
             la = ld_cur(z + 5);
             pv = ld_prev(z + 1);
@@ -244,16 +259,39 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
                                           q[7][v], q[8][v]);
             const float lap = fmaf(2.0f * kA0, q[4][v], lz + lx);
             G[v] = gzz * gxv[v];
-            nw[v] = leapfrog(G[v], q[4][v], cc[v], lap, pc[v]);
+            if constexpr (ST == kF32) {
+                nw[v] = leapfrog(G[v], q[4][v], cc[v], lap, pc[v]);
+            } else {
+                nw[v] = fmaf(G[v] * h.sc, fmaf(cc[v], lap, 2.0f * q[4][v]),
+                             -((G[v] * G[v]) * h.sp) * pc[v]);
+            }
             lp[v] = lap;
         }
-        finish_cells<ST, VX, MODE, false>(a, h, z, 0, x0, lane_in, (size_t)z * px + x0, nw, lp, cc, G,
-                                   inj, bmax);
+        const bool rec_row = has_rec && z >= a.rec.z0 && z <= rz_last &&
+                             (a.rec.dz == 1 || (z - a.rec.z0) % a.rec.dz == 0);
+        const bool src_row = MODE != kAdj && z == a.sz;
+        const size_t off = (size_t)z * px + xoff;
+        if (FULL && !rec_row && !src_row)
+            store_cells<ST, VX, MODE, false>(a, h, x0, off, nw, lp, bmax);
+        else
+            finish_cells<ST, VX, MODE, false>(a, h, z, 0, x0, lane_in, off, nw, lp, cc, G, inj,
+                                              bmax);
 #pragma unroll
         for (int k = 0; k < 8; ++k)
 #pragma unroll
             for (int v = 0; v < VX; ++v) q[k][v] = q[k + 1][v];
     }
+}
+
+template <int ST, int VX, int MODE>
+__device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
+                                            float (*row)[64 * VX + 8], const HalfCtx &h,
+                                            float inj, float &bmax)
+{
+    if ((tx + 1) * 64 * VX <= a.nx)
+        step2d_body<ST, VX, MODE, true>(a, tx, tz, row, h, inj, bmax);
+    else
+        step2d_body<ST, VX, MODE, false>(a, tx, tz, row, h, inj, bmax);
 }
 
 template <int ST, int VX, int MODE>
