@@ -210,14 +210,24 @@ __device__ __forceinline__ int32_t *max_slot(int32_t *meta, int level)
     return &meta[kMaxBase + level * kMaxSlots + (blockIdx.x & (kMaxSlots - 1))];
 }
 
-// Block-wide max of non-negative floats, folded into a slot by atomicMax on
-// the bit pattern (order-independent, hence deterministic).
+// Folds a non-negative float into a slot by atomicMax on its bit pattern
+// (order-independent, hence deterministic).  atomicMax is monotone, so a
+// block whose value does not exceed what the slot already holds may skip
+// the atomic: most blocks do, which keeps the atomics on one slot few.
+__device__ __forceinline__ void fold_max(int32_t *slot, float m)
+{
+    const uint32_t bits = __float_as_uint(m);
+    if (bits > (uint32_t)__atomic_load_n(slot, __ATOMIC_RELAXED))
+        atomicMax((unsigned int *)slot, bits);
+}
+
+// Block-wide max of non-negative floats, folded into a slot.
 template <int NT>
 __device__ __forceinline__ void block_max_to(int32_t *slot, float v, float *red)
 {
     for (int off = 32; off >= 1; off >>= 1) v = fmaxf(v, __shfl_xor(v, off, 64));
     if constexpr (NT == 64) {
-        if (threadIdx.x == 0) atomicMax((unsigned int *)slot, __float_as_uint(v));
+        if (threadIdx.x == 0) fold_max(slot, v);
     } else {
         const int w = threadIdx.x >> 6;
         __syncthreads();
@@ -226,7 +236,7 @@ __device__ __forceinline__ void block_max_to(int32_t *slot, float v, float *red)
         if (threadIdx.x == 0) {
             float m = red[0];
             for (int i = 1; i < NT / 64; ++i) m = fmaxf(m, red[i]);
-            atomicMax((unsigned int *)slot, __float_as_uint(m));
+            fold_max(slot, m);
         }
     }
 }

@@ -12,15 +12,8 @@
 // Both follow the fused step of arXiv 2311.05038, Section 7 (Listing 3's
 // add_source, fd_pzz, fd_pxx, fd_time and swap in one pass).
 #include <algorithm>
-#include <type_traits>
 
 #include "fd_device.hpp"
-
-// 1: unroll the 3D plane loop 9 times so the z register queue rotates by
-// renaming instead of moves (larger code); 0: rolled loop.
-#ifndef FD_UNROLL9
-#define FD_UNROLL9 0
-#endif
 #include "fd_launch.hpp"
 
 namespace fdk {
@@ -96,40 +89,6 @@ __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h
     }
 }
 
-// Fast epilogue for tiles wholly inside the grid on planes without
-// receivers or the source: store (and the adjoint/recompute side outputs).
-template <int ST, int VX, int MODE, bool STREAM>
-__device__ __forceinline__ void store_cells(const StepArgs &a, const HalfCtx &h, int x0, size_t off,
-                                            const float (&nw)[VX], const float (&lp)[VX],
-                                            float &bmax)
-{
-    using T = typename Stor<ST>::T;
-    T *prv = (T *)a.prev;
-    Pack<T, VX> o;
-#pragma unroll
-    for (int v = 0; v < VX; ++v) {
-        if constexpr (ST != kF32) bmax = fmaxf(bmax, fabsf(nw[v]));
-        o.v[v] = encode<ST>(nw[v], h.sn_inv);
-    }
-    if constexpr (STREAM)
-        stp_stream<T, VX>(prv + off, o);
-    else
-        stp<T, VX>(prv + off, o);
-    if constexpr (MODE == kFwdLap) {
-        Pack<float, VX> L;
-#pragma unroll
-        for (int v = 0; v < VX; ++v) L.v[v] = lp[v];
-        stp<float, VX>(a.lap + off, L);
-    }
-    if constexpr (MODE == kAdj) {
-        const Pack<float, VX> lw = ldp<float, VX>(a.lap + off);
-        Pack<double, VX> gg = ldp<double, VX>(a.g + off);
-#pragma unroll
-        for (int v = 0; v < VX; ++v) gg.v[v] = fma((double)nw[v], (double)lw.v[v], gg.v[v]);
-        stp<double, VX>(a.g + off, gg);
-    }
-}
-
 // sum_k a_k (u_{-k} + u_{+k}), k = 1..4.  The library is built with
 // -ffp-contract=off; every fused multiply-add is written out, so all kernel
 // variants round identically.
@@ -145,17 +104,29 @@ __device__ __forceinline__ float leapfrog(float G, float ctr, float c, float lap
     return fmaf(G, fmaf(c, lap, 2.0f * ctr), -(G * G) * prev);
 }
 
+// The same update on 16-bit fields read without their power-of-two scales
+// (P = sc q, Pold = sp qp, and L q computed from the unscaled q): the scales
+// go into the coefficients, (G sc)(2 q + c L q) - (G^2 sp) qp, which is
+// exactly the scaled arithmetic since multiplying by 2^k does not round.
+template <int ST>
+__device__ __forceinline__ float update(float G, float ctr, float c, float lap, float prev,
+                                        const HalfCtx &h)
+{
+    if constexpr (ST == kF32)
+        return leapfrog(G, ctr, c, lap, prev);
+    else
+        return fmaf(G * h.sc, fmaf(c, lap, 2.0f * ctr), -((G * G) * h.sp) * prev);
+}
+
 // --------------------------------------------------------------------------
 // 2D
 // --------------------------------------------------------------------------
-template <int ST, int VX, int MODE, bool FULL>
-__device__ __forceinline__ void step2d_body(const StepArgs &a, int tx, int tz,
+template <int ST, int VX, int MODE>
+__device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
                                             float (*row)[64 * VX + 8], const HalfCtx &h,
                                             float inj, float &bmax)
 {
     using T = typename Stor<ST>::T;
-    using PT = Pack<T, VX>;
-    using PF = Pack<float, VX>;
     constexpr int TX = 64 * VX;
     const int lane = threadIdx.x & 63;
     const int xb = tx * TX;
@@ -165,16 +136,13 @@ __device__ __forceinline__ void step2d_body(const StepArgs &a, int tx, int tz,
     const T *__restrict__ cur = (const T *)a.cur;
     const T *__restrict__ prv = (const T *)a.prev;
     const size_t px = (size_t)a.px;
-    const bool lane_in = FULL || x0 < a.px;
-    const size_t xoff = lane_in ? (size_t)x0 : 0;
+    const bool lane_in = x0 < a.px;
     const int nx = a.nx, nz = a.nz;
 
     float gxv[VX];
 #pragma unroll
-    for (int v = 0; v < VX; ++v) gxv[v] = (FULL || x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
+    for (int v = 0; v < VX; ++v) gxv[v] = (x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
 
-    // x-halo: lanes 0..3 take the 4 cells left of the tile, lanes 60..63 the
-    // 4 cells right of it; read at a clamped address, zeroed by select.
     int hx = -1, hslot = 0;
     if (lane < 4) {
         hx = xb - 4 + lane;
@@ -185,33 +153,27 @@ __device__ __forceinline__ void step2d_body(const StepArgs &a, int tx, int tz,
     }
     const bool hlane = (lane < 4) || (lane >= 60);
     const bool hvalid = hx >= 0 && hx < nx;
-    const size_t hoff = hvalid ? (size_t)hx : 0;
 
-    // Loads return raw packs (zero outside the grid); values are decoded,
-    // without their power-of-two scale, where they are consumed.
+    // Loads return raw packs (zero outside the grid); values are decoded
+    // where they are consumed, so a prefetch never waits for its own load.
+    using PT = Pack<T, VX>;
+    using PF = Pack<float, VX>;
     auto ld_cur = [&](int z) -> PT {
         PT p{};
-        if (z >= 0 && z < nz && lane_in) p = ldp<T, VX>(cur + (size_t)z * px + xoff);
+        if (z >= 0 && z < nz && lane_in) p = ldp<T, VX>(cur + (size_t)z * px + x0);
         return p;
     };
     auto ld_prev = [&](int z) -> PT {
         PT p{};
-        if (z < nz && lane_in) p = ldp<T, VX>(prv + (size_t)z * px + xoff);
+        if (z < nz && lane_in) p = ldp<T, VX>(prv + (size_t)z * px + x0);
         return p;
     };
     auto ld_c = [&](int z) -> PF {
         PF p{};
-        if (z < nz && lane_in) p = ldp<float, VX>(a.c + (size_t)z * px + xoff);
+        if (z < nz && lane_in) p = ldp<float, VX>(a.c + (size_t)z * px + x0);
         return p;
     };
-    auto ld_halo = [&](int z) -> T {
-        T v = (T)0;
-        if (hlane && z < nz) {
-            const T r = cur[(size_t)z * px + hoff];
-            v = hvalid ? r : (T)0;
-        }
-        return v;
-    };
+    auto ld_halo = [&](int z) -> T { return (hvalid && z < nz) ? cur[(size_t)z * px + hx] : (T)0; };
 
     float q[9][VX];
 #pragma unroll
@@ -223,10 +185,6 @@ __device__ __forceinline__ void step2d_body(const StepArgs &a, int tx, int tz,
     PT la = ld_cur(zb + 4), pv = ld_prev(zb);
     PF cv = ld_c(zb);
     T hv = ld_halo(zb);
-
-    const bool has_rec = (MODE == kAdj ? a.resid_row != nullptr : a.trace_row != nullptr) &&
-                         a.rec.nz > 0;
-    const int rz_last = a.rec.z0 + (a.rec.nz - 1) * a.rec.dz;
 
     for (int z = zb; z < ze; ++z) {
         float pc[VX], cc[VX];
@@ -259,39 +217,16 @@ __device__ __forceinline__ void step2d_body(const StepArgs &a, int tx, int tz,
                                           q[7][v], q[8][v]);
             const float lap = fmaf(2.0f * kA0, q[4][v], lz + lx);
             G[v] = gzz * gxv[v];
-            if constexpr (ST == kF32) {
-                nw[v] = leapfrog(G[v], q[4][v], cc[v], lap, pc[v]);
-            } else {
-                nw[v] = fmaf(G[v] * h.sc, fmaf(cc[v], lap, 2.0f * q[4][v]),
-                             -((G[v] * G[v]) * h.sp) * pc[v]);
-            }
+            nw[v] = update<ST>(G[v], q[4][v], cc[v], lap, pc[v], h);
             lp[v] = lap;
         }
-        const bool rec_row = has_rec && z >= a.rec.z0 && z <= rz_last &&
-                             (a.rec.dz == 1 || (z - a.rec.z0) % a.rec.dz == 0);
-        const bool src_row = MODE != kAdj && z == a.sz;
-        const size_t off = (size_t)z * px + xoff;
-        if (FULL && !rec_row && !src_row)
-            store_cells<ST, VX, MODE, false>(a, h, x0, off, nw, lp, bmax);
-        else
-            finish_cells<ST, VX, MODE, false>(a, h, z, 0, x0, lane_in, off, nw, lp, cc, G, inj,
-                                              bmax);
+        finish_cells<ST, VX, MODE, false>(a, h, z, 0, x0, lane_in, (size_t)z * px + x0, nw, lp, cc, G,
+                                   inj, bmax);
 #pragma unroll
         for (int k = 0; k < 8; ++k)
 #pragma unroll
             for (int v = 0; v < VX; ++v) q[k][v] = q[k + 1][v];
     }
-}
-
-template <int ST, int VX, int MODE>
-__device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
-                                            float (*row)[64 * VX + 8], const HalfCtx &h,
-                                            float inj, float &bmax)
-{
-    if ((tx + 1) * 64 * VX <= a.nx)
-        step2d_body<ST, VX, MODE, true>(a, tx, tz, row, h, inj, bmax);
-    else
-        step2d_body<ST, VX, MODE, false>(a, tx, tz, row, h, inj, bmax);
 }
 
 template <int ST, int VX, int MODE>
@@ -331,101 +266,97 @@ __global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
 // --------------------------------------------------------------------------
 // 3D
 // --------------------------------------------------------------------------
-// One block's tile, tz-th z-chunk.  FULL: every cell of the tile and every
-// y-halo row lies inside the grid, so loads need no per-lane or per-row
-// tests (z tests are uniform).  Fields are decoded without their power-of-two
-// scale; the scales are folded into the update, which is exact:
-//   new = (G sc)(2 q + c L q) - (G^2 sp) qp   with P = sc q, Pold = sp qp.
-template <int ST, int VX, int RY, int NW, int MODE, bool FULL>
-__device__ __forceinline__ float step3d_body(const StepArgs &a, float *__restrict__ plane,
-                                             int xb, int yb, int zb, int ze, const HalfCtx &h,
-                                             float inj)
+template <int ST, int VX, int RY, int NW, int MODE>
+__global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
 {
     using T = typename Stor<ST>::T;
+    static_assert(NW == 2 || NW == 4 || NW == 8, "waves per block");
     constexpr int TX = 64 * VX, TY = NW * RY, LW = TX + 8, LH = TY + 8, HH = 8 / NW;
-    using PT = Pack<T, VX>;
-    using PF = Pack<float, VX>;
+    __shared__ float pl[2][LH * LW];
+    __shared__ float red[NW];
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
-    const int x0 = xb + lane * VX;
+    const int nb = a.tiles_x * a.tiles_y * a.tiles_z;
+    const int t = xcd_tile(blockIdx.x, nb);
+    const int tx = t % a.tiles_x;
+    const int t2 = t / a.tiles_x;
+    const int ty = t2 % a.tiles_y, tz = t2 / a.tiles_y;
+    const int xb = tx * TX, yb = ty * TY, x0 = xb + lane * VX;
+    const int zb = tz * a.zc, ze = min(zb + a.zc, a.nz);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t px = (size_t)a.px, pp = (size_t)ny * px;
-    const bool lane_in = FULL || x0 < a.px;
+    const bool lane_in = x0 < a.px;
     const T *__restrict__ cur = (const T *)a.cur;
     const T *__restrict__ prv = (const T *)a.prev;
+
+    float inj = 0.0f;
+    if constexpr (MODE != kAdj)
+        if (a.n + 1 < a.nt) inj = a.amp * a.wavelet[a.n + 1];
+    const HalfCtx h = half_prologue<ST>(a, inj, blockIdx.x == 0);
 
     int yj[RY];
     bool yin[RY];
     float gyv[RY];
-    size_t rowoff[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
         yj[j] = yb + wy + NW * j;
-        yin[j] = FULL || yj[j] < ny;
+        yin[j] = yj[j] < ny;
         gyv[j] = yin[j] ? a.gy[yj[j]] : 0.0f;
-        rowoff[j] = (size_t)(yin[j] ? yj[j] : 0) * px + (lane_in ? x0 : 0);
     }
     float gxv[VX];
 #pragma unroll
-    for (int v = 0; v < VX; ++v) gxv[v] = (FULL || x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
+    for (int v = 0; v < VX; ++v) gxv[v] = (x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
 
-    // y-halo rows of this thread: k = wy + NW hh, hh < 8 / NW.
-    size_t hyoff[HH];
-    int hyslot[HH];
+    // y-halo rows handled by this thread: k = wy + NW hh, hh < 8 / NW.
+    int hy[HH], hyslot[HH];
     bool hyv[HH];
 #pragma unroll
     for (int hh = 0; hh < HH; ++hh) {
         const int k = wy + NW * hh;
         const int ly = k < 4 ? k - 4 : TY + k - 4;
-        const int yy = yb + ly;
-        hyv[hh] = FULL || (yy >= 0 && yy < ny && lane_in);
-        hyoff[hh] = (size_t)(hyv[hh] ? yy : 0) * px + (lane_in ? x0 : 0);
+        hy[hh] = yb + ly;
+        hyv[hh] = hy[hh] >= 0 && hy[hh] < ny && lane_in;
         hyslot[hh] = (ly + 4) * LW + 4 + lane * VX;
     }
-    // x-halo cell of this thread (threads < 8 TY); read at a clamped address
-    // and zeroed by select when it lies outside the grid.
+    // x-halo cell handled by this thread (threads < 8 TY).
     const bool hxl = threadIdx.x < 8 * TY;
-    size_t hxoff = 0;
-    int hxslot = 0;
-    bool hxv = false;
+    int hxx = 0, hxy = 0, hxslot = 0;
     if (hxl) {
         const int lr = threadIdx.x >> 3, ci = threadIdx.x & 7;
-        const int xx = ci < 4 ? xb - 4 + ci : xb + TX + ci - 4;
-        const int yy = yb + lr;
-        hxv = xx >= 0 && xx < nx && yy < ny;
-        hxoff = hxv ? (size_t)yy * px + xx : 0;
+        hxx = ci < 4 ? xb - 4 + ci : xb + TX + ci - 4;
+        hxy = yb + lr;
         hxslot = (lr + 4) * LW + (ci < 4 ? ci : TX + ci);
     }
+    const bool hxv = hxl && hxx >= 0 && hxx < nx && hxy < ny;
 
-    auto ld3 = [&](const T *base, int z, int j) -> PT {
+    // Loads return raw packs (zero outside the grid); values are decoded
+    // where they are consumed, so a prefetch never waits for its own load.
+    using PT = Pack<T, VX>;
+    using PF = Pack<float, VX>;
+    auto ld3 = [&](const T *base, int z, int y) -> PT {
         PT p{};
-        if (z >= 0 && z < nz && (FULL || yin[j] && lane_in))
-            p = ldp<T, VX>(base + (size_t)z * pp + rowoff[j]);
+        if (z >= 0 && z < nz && y < ny && lane_in)
+            p = ldp<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
         return p;
     };
-    auto ld3nt = [&](const T *base, int z, int j) -> PT {
+    auto ld3nt = [&](const T *base, int z, int y) -> PT {
         PT p{};
-        if (z < nz && (FULL || yin[j] && lane_in))
-            p = ldp_stream<T, VX>(base + (size_t)z * pp + rowoff[j]);
+        if (z < nz && y < ny && lane_in)
+            p = ldp_stream<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
         return p;
     };
-    auto ldc3 = [&](int z, int j) -> PF {
+    auto ldc3 = [&](int z, int y) -> PF {
         PF p{};
-        if (z < nz && (FULL || yin[j] && lane_in))
-            p = ldp_stream<float, VX>(a.c + (size_t)z * pp + rowoff[j]);
+        if (z < nz && y < ny && lane_in)
+            p = ldp_stream<float, VX>(a.c + (size_t)z * pp + (size_t)y * px + x0);
         return p;
     };
     auto ldhy = [&](int z, int hh) -> PT {
         PT p{};
-        if (z < nz && hyv[hh]) p = ldp<T, VX>(cur + (size_t)z * pp + hyoff[hh]);
+        if (hyv[hh] && z < nz) p = ldp<T, VX>(cur + (size_t)z * pp + (size_t)hy[hh] * px + x0);
         return p;
     };
     auto ldhx = [&](int z) -> T {
-        T v = (T)0;
-        if (hxl && z < nz) {
-            const T r = cur[(size_t)z * pp + hxoff];
-            v = hxv ? r : (T)0;
-        }
-        return v;
+        return (hxv && z < nz) ? cur[(size_t)z * pp + (size_t)hxy * px + hxx] : (T)0;
     };
 
     float q[RY][9][VX];
@@ -433,7 +364,7 @@ __device__ __forceinline__ float step3d_body(const StepArgs &a, float *__restric
     for (int j = 0; j < RY; ++j)
 #pragma unroll
         for (int k = 0; k < 8; ++k) {
-            const PT p = ld3(cur, zb - 4 + k, j);
+            const PT p = ld3(cur, zb - 4 + k, yj[j]);
 #pragma unroll
             for (int v = 0; v < VX; ++v) q[j][k][v] = decode<ST>(p.v[v], 1.0f);
         }
@@ -441,31 +372,22 @@ __device__ __forceinline__ float step3d_body(const StepArgs &a, float *__restric
     PF cv[RY];
 #pragma unroll
     for (int j = 0; j < RY; ++j) {
-        la[j] = ld3(cur, zb + 4, j);
-        pv[j] = ld3nt(prv, zb, j);
-        cv[j] = ldc3(zb, j);
+        la[j] = ld3(cur, zb + 4, yj[j]);
+        pv[j] = ld3nt(prv, zb, yj[j]);
+        cv[j] = ldc3(zb, yj[j]);
     }
 #pragma unroll
     for (int hh = 0; hh < HH; ++hh) yh[hh] = ldhy(zb, hh);
     T xh = ldhx(zb);
     float bmax = 0.0f;
 
-    // receiver planes and the source plane are rare: uniform per-plane tests
-    const bool has_rec = (MODE == kAdj ? a.resid_row != nullptr : a.trace_row != nullptr) &&
-                         a.rec.nz > 0;
-    const int rz_last = a.rec.z0 + (a.rec.nz - 1) * a.rec.dz;
-
-    // One plane.  The 9-deep register queue is rotated by renaming: at phase
-    // PH (= (z - zb) mod 9) plane z - 4 + k lives in slot (k + PH) mod 9, so
-    // no value moves; the loop below is unrolled 9 times.
-    auto plane_step = [&](auto phase, int z) {
-        constexpr int PH = decltype(phase)::value;
+    for (int z = zb; z < ze; ++z) {
         float pc[RY][VX], cc[RY][VX], yhc[HH][VX];
 #pragma unroll
         for (int j = 0; j < RY; ++j)
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
-                q[j][(8 + PH) % 9][v] = decode<ST>(la[j].v[v], 1.0f);
+                q[j][8][v] = decode<ST>(la[j].v[v], 1.0f);
                 pc[j][v] = decode<ST>(pv[j].v[v], 1.0f);
                 cc[j][v] = cv[j].v[v];
             }
@@ -477,20 +399,19 @@ __device__ __forceinline__ float step3d_body(const StepArgs &a, float *__restric
         if (z + 1 < ze) {
 #pragma unroll
             for (int j = 0; j < RY; ++j) {
-                la[j] = ld3(cur, z + 5, j);
-                pv[j] = ld3nt(prv, z + 1, j);
-                cv[j] = ldc3(z + 1, j);
+                la[j] = ld3(cur, z + 5, yj[j]);
+                pv[j] = ld3nt(prv, z + 1, yj[j]);
+                cv[j] = ldc3(z + 1, yj[j]);
             }
 #pragma unroll
             for (int hh = 0; hh < HH; ++hh) yh[hh] = ldhy(z + 1, hh);
             xh = ldhx(z + 1);
         }
-        float *P = plane + (z & 1) * (LH * LW);
+        float *P = pl[z & 1];
 #pragma unroll
         for (int j = 0; j < RY; ++j)
 #pragma unroll
-            for (int v = 0; v < VX; ++v)
-                P[(wy + NW * j + 4) * LW + 4 + lane * VX + v] = q[j][(4 + PH) % 9][v];
+            for (int v = 0; v < VX; ++v) P[(wy + NW * j + 4) * LW + 4 + lane * VX + v] = q[j][4][v];
 #pragma unroll
         for (int hh = 0; hh < HH; ++hh)
 #pragma unroll
@@ -498,9 +419,6 @@ __device__ __forceinline__ float step3d_body(const StepArgs &a, float *__restric
         if (hxl) P[hxslot] = xhc;
         __syncthreads();
         const float gzz = a.gz[z];
-        const bool rec_plane = has_rec && z >= a.rec.z0 && z <= rz_last &&
-                               (a.rec.dz == 1 || (z - a.rec.z0) % a.rec.dz == 0);
-        const bool src_plane = MODE != kAdj && z == a.sz;
 #pragma unroll
         for (int j = 0; j < RY; ++j) {
             float nw[VX], lp[VX], G[VX];
@@ -512,34 +430,17 @@ __device__ __forceinline__ float step3d_body(const StepArgs &a, float *__restric
                 const float lyv = stencil_taps(P[li - 4 * LW], P[li - 3 * LW], P[li - 2 * LW],
                                                P[li - LW], P[li + LW], P[li + 2 * LW],
                                                P[li + 3 * LW], P[li + 4 * LW]);
-                const float lz = stencil_taps(q[j][(0 + PH) % 9][v], q[j][(1 + PH) % 9][v],
-                                              q[j][(2 + PH) % 9][v], q[j][(3 + PH) % 9][v],
-                                              q[j][(5 + PH) % 9][v], q[j][(6 + PH) % 9][v],
-                                              q[j][(7 + PH) % 9][v], q[j][(8 + PH) % 9][v]);
-                const float ctr = q[j][(4 + PH) % 9][v];
-                const float lap = fmaf(3.0f * kA0, ctr, lz + (lyv + lx));
+                const float lz = stencil_taps(q[j][0][v], q[j][1][v], q[j][2][v], q[j][3][v],
+                                              q[j][5][v], q[j][6][v], q[j][7][v], q[j][8][v]);
+                const float lap = fmaf(3.0f * kA0, q[j][4][v], lz + (lyv + lx));
                 G[v] = (gzz * gyv[j]) * gxv[v];
-                if constexpr (ST == kF32) {
-                    nw[v] = leapfrog(G[v], ctr, cc[j][v], lap, pc[j][v]);
-                } else {
-                    nw[v] = fmaf(G[v] * h.sc, fmaf(cc[j][v], lap, 2.0f * ctr),
-                                 -((G[v] * G[v]) * h.sp) * pc[j][v]);
-                }
+                nw[v] = update<ST>(G[v], q[j][4][v], cc[j][v], lap, pc[j][v], h);
                 lp[v] = lap;
             }
-            const size_t off = (size_t)z * pp + rowoff[j];
-            if (FULL && !rec_plane && !src_plane) {
-                store_cells<ST, VX, MODE, true>(a, h, x0, off, nw, lp, bmax);
-            } else {
-                finish_cells<ST, VX, MODE, true>(a, h, z, yj[j], x0, lane_in && yin[j], off, nw,
-                                                 lp, cc[j], G, inj, bmax);
-            }
+            finish_cells<ST, VX, MODE, true>(a, h, z, yj[j], x0, lane_in && yin[j],
+                                       (size_t)z * pp + (size_t)yj[j] * px + x0, nw, lp, cc[j],
+                                       G, inj, bmax);
         }
-    };
-    using std::integral_constant;
-#if !FD_UNROLL9
-    for (int z = zb; z < ze; ++z) {
-        plane_step(integral_constant<int, 0>{}, z);
 #pragma unroll
         for (int j = 0; j < RY; ++j)
 #pragma unroll
@@ -547,54 +448,6 @@ __device__ __forceinline__ float step3d_body(const StepArgs &a, float *__restric
 #pragma unroll
                 for (int v = 0; v < VX; ++v) q[j][k][v] = q[j][k + 1][v];
     }
-#else
-    for (int z = zb; z < ze; z += 9) {
-        plane_step(integral_constant<int, 0>{}, z);
-        if (z + 1 >= ze) break;
-        plane_step(integral_constant<int, 1>{}, z + 1);
-        if (z + 2 >= ze) break;
-        plane_step(integral_constant<int, 2>{}, z + 2);
-        if (z + 3 >= ze) break;
-        plane_step(integral_constant<int, 3>{}, z + 3);
-        if (z + 4 >= ze) break;
-        plane_step(integral_constant<int, 4>{}, z + 4);
-        if (z + 5 >= ze) break;
-        plane_step(integral_constant<int, 5>{}, z + 5);
-        if (z + 6 >= ze) break;
-        plane_step(integral_constant<int, 6>{}, z + 6);
-        if (z + 7 >= ze) break;
-        plane_step(integral_constant<int, 7>{}, z + 7);
-        if (z + 8 >= ze) break;
-        plane_step(integral_constant<int, 8>{}, z + 8);
-    }
-#endif
-    return bmax;
-}
-
-template <int ST, int VX, int RY, int NW, int MODE>
-__global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
-{
-    static_assert(NW == 2 || NW == 4 || NW == 8, "waves per block");
-    constexpr int TX = 64 * VX, TY = NW * RY, LW = TX + 8, LH = TY + 8;
-    __shared__ float pl[2 * LH * LW];
-    __shared__ float red[NW];
-    const int nb = a.tiles_x * a.tiles_y * a.tiles_z;
-    const int t = xcd_tile(blockIdx.x, nb);
-    const int tx = t % a.tiles_x;
-    const int t2 = t / a.tiles_x;
-    const int ty = t2 % a.tiles_y, tz = t2 / a.tiles_y;
-    const int xb = tx * TX, yb = ty * TY;
-    const int zb = tz * a.zc, ze = min(zb + a.zc, a.nz);
-    float inj = 0.0f;
-    if constexpr (MODE != kAdj)
-        if (a.n + 1 < a.nt) inj = a.amp * a.wavelet[a.n + 1];
-    const HalfCtx h = half_prologue<ST>(a, inj, blockIdx.x == 0);
-    const bool full = xb + TX <= a.nx && yb >= 4 && yb + TY + 4 <= a.ny;
-    float bmax;
-    if (full)
-        bmax = step3d_body<ST, VX, RY, NW, MODE, true>(a, pl, xb, yb, zb, ze, h, inj);
-    else
-        bmax = step3d_body<ST, VX, RY, NW, MODE, false>(a, pl, xb, yb, zb, ze, h, inj);
     if constexpr (ST != kF32) block_max_to<64 * NW>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax, red);
 }
 
@@ -806,7 +659,6 @@ hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, i
 #ifndef FD_3D_VX32
 #define FD_3D_VX32 4
 #endif
-
 #ifndef FD_3D_RY32
 #define FD_3D_RY32 2
 #endif
