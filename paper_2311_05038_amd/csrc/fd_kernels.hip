@@ -13,8 +13,16 @@
 // add_source, fd_pzz, fd_pxx, fd_time and swap in one pass).
 #include <algorithm>
 
+#include <type_traits>
+
 #include "fd_device.hpp"
 #include "fd_launch.hpp"
+
+// 1: unroll the 3D plane loop 9 times so the z register queue rotates by
+// renaming instead of moves (larger code); 0: rolled loop.
+#ifndef FD_UNROLL9
+#define FD_UNROLL9 0
+#endif
 
 namespace fdk {
 
@@ -381,13 +389,18 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
     T xh = ldhx(zb);
     float bmax = 0.0f;
 
-    for (int z = zb; z < ze; ++z) {
+    // One plane.  At phase PH, plane z - 4 + k of the register queue sits in
+    // slot (k + PH) mod 9.  With FD_UNROLL9 the plane loop is unrolled 9
+    // times so the queue rotates by renaming; otherwise it runs at phase 0
+    // and the values shift down one slot per plane.
+    auto plane_step = [&](auto phase, int z) {
+        constexpr int PH = decltype(phase)::value;
         float pc[RY][VX], cc[RY][VX], yhc[HH][VX];
 #pragma unroll
         for (int j = 0; j < RY; ++j)
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
-                q[j][8][v] = decode<ST>(la[j].v[v], 1.0f);
+                q[j][(8 + PH) % 9][v] = decode<ST>(la[j].v[v], 1.0f);
                 pc[j][v] = decode<ST>(pv[j].v[v], 1.0f);
                 cc[j][v] = cv[j].v[v];
             }
@@ -411,7 +424,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
 #pragma unroll
         for (int j = 0; j < RY; ++j)
 #pragma unroll
-            for (int v = 0; v < VX; ++v) P[(wy + NW * j + 4) * LW + 4 + lane * VX + v] = q[j][4][v];
+            for (int v = 0; v < VX; ++v) P[(wy + NW * j + 4) * LW + 4 + lane * VX + v] = q[j][(4 + PH) % 9][v];
 #pragma unroll
         for (int hh = 0; hh < HH; ++hh)
 #pragma unroll
@@ -430,17 +443,44 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                 const float lyv = stencil_taps(P[li - 4 * LW], P[li - 3 * LW], P[li - 2 * LW],
                                                P[li - LW], P[li + LW], P[li + 2 * LW],
                                                P[li + 3 * LW], P[li + 4 * LW]);
-                const float lz = stencil_taps(q[j][0][v], q[j][1][v], q[j][2][v], q[j][3][v],
-                                              q[j][5][v], q[j][6][v], q[j][7][v], q[j][8][v]);
-                const float lap = fmaf(3.0f * kA0, q[j][4][v], lz + (lyv + lx));
+                const float lz = stencil_taps(q[j][(0 + PH) % 9][v], q[j][(1 + PH) % 9][v],
+                                              q[j][(2 + PH) % 9][v], q[j][(3 + PH) % 9][v],
+                                              q[j][(5 + PH) % 9][v], q[j][(6 + PH) % 9][v],
+                                              q[j][(7 + PH) % 9][v], q[j][(8 + PH) % 9][v]);
+                const float lap = fmaf(3.0f * kA0, q[j][(4 + PH) % 9][v], lz + (lyv + lx));
                 G[v] = (gzz * gyv[j]) * gxv[v];
-                nw[v] = update<ST>(G[v], q[j][4][v], cc[j][v], lap, pc[j][v], h);
+                nw[v] = update<ST>(G[v], q[j][(4 + PH) % 9][v], cc[j][v], lap, pc[j][v], h);
                 lp[v] = lap;
             }
             finish_cells<ST, VX, MODE, true>(a, h, z, yj[j], x0, lane_in && yin[j],
                                        (size_t)z * pp + (size_t)yj[j] * px + x0, nw, lp, cc[j],
                                        G, inj, bmax);
         }
+    };
+    using std::integral_constant;
+#if FD_UNROLL9
+    for (int z = zb; z < ze; z += 9) {
+        plane_step(integral_constant<int, 0>{}, z);
+        if (z + 1 >= ze) break;
+        plane_step(integral_constant<int, 1>{}, z + 1);
+        if (z + 2 >= ze) break;
+        plane_step(integral_constant<int, 2>{}, z + 2);
+        if (z + 3 >= ze) break;
+        plane_step(integral_constant<int, 3>{}, z + 3);
+        if (z + 4 >= ze) break;
+        plane_step(integral_constant<int, 4>{}, z + 4);
+        if (z + 5 >= ze) break;
+        plane_step(integral_constant<int, 5>{}, z + 5);
+        if (z + 6 >= ze) break;
+        plane_step(integral_constant<int, 6>{}, z + 6);
+        if (z + 7 >= ze) break;
+        plane_step(integral_constant<int, 7>{}, z + 7);
+        if (z + 8 >= ze) break;
+        plane_step(integral_constant<int, 8>{}, z + 8);
+    }
+#else
+    for (int z = zb; z < ze; ++z) {
+        plane_step(integral_constant<int, 0>{}, z);
 #pragma unroll
         for (int j = 0; j < RY; ++j)
 #pragma unroll
@@ -448,6 +488,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
 #pragma unroll
                 for (int v = 0; v < VX; ++v) q[j][k][v] = q[j][k + 1][v];
     }
+#endif
     if constexpr (ST != kF32) block_max_to<64 * NW>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax, red);
 }
 
