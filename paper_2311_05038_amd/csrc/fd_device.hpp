@@ -121,6 +121,10 @@ __device__ __forceinline__ void stp_stream(T *p, const Pack<T, VX> &x)
 #endif
 }
 
+#ifndef FD_F16_BITS
+#define FD_F16_BITS 1
+#endif
+
 template <int ST>
 __device__ __forceinline__ float decode(typename Stor<ST>::T q, float scale)
 {
@@ -132,6 +136,28 @@ __device__ __forceinline__ float decode(typename Stor<ST>::T q, float scale)
         return __uint_as_float((uint32_t)q << 16) * scale;
     }
 }
+
+// binary16 code -> FP32 value times 2^-112, by moving the sign to bit 31 and
+// the 15 exponent/significand bits to bits 13..27.  Exact for every finite
+// code, subnormals included (FP32 keeps subnormals here).
+__device__ __forceinline__ float f16_bits_scaled(uint16_t q)
+{
+    const uint32_t u = q;
+    return __uint_as_float(((u & 0x8000u) << 16) | ((u & 0x7FFFu) << 13));
+}
+
+// Decode used inside the step kernels, before the power-of-two field scale:
+// FP32 and bfloat16 exactly, binary16 either exactly (hardware conversion)
+// or times 2^-112 (bit move; the step applies kF16Unscale once per cell).
+template <int ST>
+__device__ __forceinline__ float decode_raw(typename Stor<ST>::T q)
+{
+    if constexpr (ST == kF16 && FD_F16_BITS)
+        return f16_bits_scaled(q);
+    else
+        return decode<ST>(q, 1.0f);
+}
+constexpr float kF16Unscale = 5.192296858534828e+33f;  // 2^112
 
 // Round-to-nearest-even encode of x * inv_scale.
 template <int ST>

@@ -120,10 +120,15 @@ template <int ST>
 __device__ __forceinline__ float update(float G, float ctr, float c, float lap, float prev,
                                         const HalfCtx &h)
 {
-    if constexpr (ST == kF32)
+    if constexpr (ST == kF32) {
         return leapfrog(G, ctr, c, lap, prev);
-    else
+    } else if constexpr (ST == kF16 && FD_F16_BITS) {
+        // operands carry 2^-112 (decode_raw); restore it before the scales
+        return fmaf(G * h.sc, fmaf(c, lap, 2.0f * ctr) * kF16Unscale,
+                    -((G * G) * h.sp) * (prev * kF16Unscale));
+    } else {
         return fmaf(G * h.sc, fmaf(c, lap, 2.0f * ctr), -((G * G) * h.sp) * prev);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -188,7 +193,7 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
     for (int k = 0; k < 8; ++k) {
         const PT p = ld_cur(zb - 4 + k);
 #pragma unroll
-        for (int v = 0; v < VX; ++v) q[k][v] = decode<ST>(p.v[v], 1.0f);
+        for (int v = 0; v < VX; ++v) q[k][v] = decode_raw<ST>(p.v[v]);
     }
     PT la = ld_cur(zb + 4), pv = ld_prev(zb);
     PF cv = ld_c(zb);
@@ -198,11 +203,11 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
         float pc[VX], cc[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
-            q[8][v] = decode<ST>(la.v[v], 1.0f);
-            pc[v] = decode<ST>(pv.v[v], 1.0f);
+            q[8][v] = decode_raw<ST>(la.v[v]);
+            pc[v] = decode_raw<ST>(pv.v[v]);
             cc[v] = cv.v[v];
         }
-        const float hc = decode<ST>(hv, 1.0f);
+        const float hc = decode_raw<ST>(hv);
         if (z + 1 < ze) {
             la = ld_cur(z + 5);
             pv = ld_prev(z + 1);
@@ -374,7 +379,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
         for (int k = 0; k < 8; ++k) {
             const PT p = ld3(cur, zb - 4 + k, yj[j]);
 #pragma unroll
-            for (int v = 0; v < VX; ++v) q[j][k][v] = decode<ST>(p.v[v], 1.0f);
+            for (int v = 0; v < VX; ++v) q[j][k][v] = decode_raw<ST>(p.v[v]);
         }
     PT la[RY], pv[RY], yh[HH];
     PF cv[RY];
@@ -400,15 +405,15 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
         for (int j = 0; j < RY; ++j)
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
-                q[j][(8 + PH) % 9][v] = decode<ST>(la[j].v[v], 1.0f);
-                pc[j][v] = decode<ST>(pv[j].v[v], 1.0f);
+                q[j][(8 + PH) % 9][v] = decode_raw<ST>(la[j].v[v]);
+                pc[j][v] = decode_raw<ST>(pv[j].v[v]);
                 cc[j][v] = cv[j].v[v];
             }
 #pragma unroll
         for (int hh = 0; hh < HH; ++hh)
 #pragma unroll
-            for (int v = 0; v < VX; ++v) yhc[hh][v] = decode<ST>(yh[hh].v[v], 1.0f);
-        const float xhc = decode<ST>(xh, 1.0f);
+            for (int v = 0; v < VX; ++v) yhc[hh][v] = decode_raw<ST>(yh[hh].v[v]);
+        const float xhc = decode_raw<ST>(xh);
         if (z + 1 < ze) {
 #pragma unroll
             for (int j = 0; j < RY; ++j) {
