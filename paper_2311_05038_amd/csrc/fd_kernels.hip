@@ -23,6 +23,10 @@
 #ifndef FD_UNROLL9
 #define FD_UNROLL9 0
 #endif
+// 1: tiles wholly inside the grid take a path without per-lane load tests.
+#ifndef FD_FULL_TILES
+#define FD_FULL_TILES 1
+#endif
 
 namespace fdk {
 
@@ -306,194 +310,203 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
         if (a.n + 1 < a.nt) inj = a.amp * a.wavelet[a.n + 1];
     const HalfCtx h = half_prologue<ST>(a, inj, blockIdx.x == 0);
 
-    int yj[RY];
-    bool yin[RY];
-    float gyv[RY];
-#pragma unroll
-    for (int j = 0; j < RY; ++j) {
-        yj[j] = yb + wy + NW * j;
-        yin[j] = yj[j] < ny;
-        gyv[j] = yin[j] ? a.gy[yj[j]] : 0.0f;
-    }
-    float gxv[VX];
-#pragma unroll
-    for (int v = 0; v < VX; ++v) gxv[v] = (x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
-
-    // y-halo rows handled by this thread: k = wy + NW hh, hh < 8 / NW.
-    int hy[HH], hyslot[HH];
-    bool hyv[HH];
-#pragma unroll
-    for (int hh = 0; hh < HH; ++hh) {
-        const int k = wy + NW * hh;
-        const int ly = k < 4 ? k - 4 : TY + k - 4;
-        hy[hh] = yb + ly;
-        hyv[hh] = hy[hh] >= 0 && hy[hh] < ny && lane_in;
-        hyslot[hh] = (ly + 4) * LW + 4 + lane * VX;
-    }
-    // x-halo cell handled by this thread (threads < 8 TY).
-    const bool hxl = threadIdx.x < 8 * TY;
-    int hxx = 0, hxy = 0, hxslot = 0;
-    if (hxl) {
-        const int lr = threadIdx.x >> 3, ci = threadIdx.x & 7;
-        hxx = ci < 4 ? xb - 4 + ci : xb + TX + ci - 4;
-        hxy = yb + lr;
-        hxslot = (lr + 4) * LW + (ci < 4 ? ci : TX + ci);
-    }
-    const bool hxv = hxl && hxx >= 0 && hxx < nx && hxy < ny;
-
-    // Loads return raw packs (zero outside the grid); values are decoded
-    // where they are consumed, so a prefetch never waits for its own load.
-    using PT = Pack<T, VX>;
-    using PF = Pack<float, VX>;
-    auto ld3 = [&](const T *base, int z, int y) -> PT {
-        PT p{};
-        if (z >= 0 && z < nz && y < ny && lane_in)
-            p = ldp<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
-        return p;
-    };
-    auto ld3nt = [&](const T *base, int z, int y) -> PT {
-        PT p{};
-        if (z < nz && y < ny && lane_in)
-            p = ldp_stream<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
-        return p;
-    };
-    auto ldc3 = [&](int z, int y) -> PF {
-        PF p{};
-        if (z < nz && y < ny && lane_in)
-            p = ldp_stream<float, VX>(a.c + (size_t)z * pp + (size_t)y * px + x0);
-        return p;
-    };
-    auto ldhy = [&](int z, int hh) -> PT {
-        PT p{};
-        if (hyv[hh] && z < nz) p = ldp<T, VX>(cur + (size_t)z * pp + (size_t)hy[hh] * px + x0);
-        return p;
-    };
-    auto ldhx = [&](int z) -> T {
-        return (hxv && z < nz) ? cur[(size_t)z * pp + (size_t)hxy * px + hxx] : (T)0;
-    };
-
-    float q[RY][9][VX];
-#pragma unroll
-    for (int j = 0; j < RY; ++j)
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const PT p = ld3(cur, zb - 4 + k, yj[j]);
-#pragma unroll
-            for (int v = 0; v < VX; ++v) q[j][k][v] = decode_raw<ST>(p.v[v]);
-        }
-    PT la[RY], pv[RY], yh[HH];
-    PF cv[RY];
-#pragma unroll
-    for (int j = 0; j < RY; ++j) {
-        la[j] = ld3(cur, zb + 4, yj[j]);
-        pv[j] = ld3nt(prv, zb, yj[j]);
-        cv[j] = ldc3(zb, yj[j]);
-    }
-#pragma unroll
-    for (int hh = 0; hh < HH; ++hh) yh[hh] = ldhy(zb, hh);
-    T xh = ldhx(zb);
-    float bmax = 0.0f;
-
-    // One plane.  At phase PH, plane z - 4 + k of the register queue sits in
-    // slot (k + PH) mod 9.  With FD_UNROLL9 the plane loop is unrolled 9
-    // times so the queue rotates by renaming; otherwise it runs at phase 0
-    // and the values shift down one slot per plane.
-    auto plane_step = [&](auto phase, int z) {
-        constexpr int PH = decltype(phase)::value;
-        float pc[RY][VX], cc[RY][VX], yhc[HH][VX];
-#pragma unroll
-        for (int j = 0; j < RY; ++j)
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                q[j][(8 + PH) % 9][v] = decode_raw<ST>(la[j].v[v]);
-                pc[j][v] = decode_raw<ST>(pv[j].v[v]);
-                cc[j][v] = cv[j].v[v];
-            }
-#pragma unroll
-        for (int hh = 0; hh < HH; ++hh)
-#pragma unroll
-            for (int v = 0; v < VX; ++v) yhc[hh][v] = decode_raw<ST>(yh[hh].v[v]);
-        const float xhc = decode_raw<ST>(xh);
-        if (z + 1 < ze) {
-#pragma unroll
-            for (int j = 0; j < RY; ++j) {
-                la[j] = ld3(cur, z + 5, yj[j]);
-                pv[j] = ld3nt(prv, z + 1, yj[j]);
-                cv[j] = ldc3(z + 1, yj[j]);
-            }
-#pragma unroll
-            for (int hh = 0; hh < HH; ++hh) yh[hh] = ldhy(z + 1, hh);
-            xh = ldhx(z + 1);
-        }
-        float *P = pl[z & 1];
-#pragma unroll
-        for (int j = 0; j < RY; ++j)
-#pragma unroll
-            for (int v = 0; v < VX; ++v) P[(wy + NW * j + 4) * LW + 4 + lane * VX + v] = q[j][(4 + PH) % 9][v];
-#pragma unroll
-        for (int hh = 0; hh < HH; ++hh)
-#pragma unroll
-            for (int v = 0; v < VX; ++v) P[hyslot[hh] + v] = yhc[hh][v];
-        if (hxl) P[hxslot] = xhc;
-        __syncthreads();
-        const float gzz = a.gz[z];
-#pragma unroll
+    // FULL: every lane's cells, every row and every y-halo row of the tile
+    // lie inside the grid, so loads need no per-lane or per-row tests (the z
+    // tests are uniform); other tiles take the checked path.
+    auto tile = [&](auto full_c) -> float {
+        constexpr bool FULL = decltype(full_c)::value;
+        int yj[RY];
+        bool yin[RY];
+        float gyv[RY];
+    #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            float nw[VX], lp[VX], G[VX];
-#pragma unroll
-            for (int v = 0; v < VX; ++v) {
-                const int li = (wy + NW * j + 4) * LW + 4 + lane * VX + v;
-                const float lx = stencil_taps(P[li - 4], P[li - 3], P[li - 2], P[li - 1], P[li + 1],
-                                              P[li + 2], P[li + 3], P[li + 4]);
-                const float lyv = stencil_taps(P[li - 4 * LW], P[li - 3 * LW], P[li - 2 * LW],
-                                               P[li - LW], P[li + LW], P[li + 2 * LW],
-                                               P[li + 3 * LW], P[li + 4 * LW]);
-                const float lz = stencil_taps(q[j][(0 + PH) % 9][v], q[j][(1 + PH) % 9][v],
-                                              q[j][(2 + PH) % 9][v], q[j][(3 + PH) % 9][v],
-                                              q[j][(5 + PH) % 9][v], q[j][(6 + PH) % 9][v],
-                                              q[j][(7 + PH) % 9][v], q[j][(8 + PH) % 9][v]);
-                const float lap = fmaf(3.0f * kA0, q[j][(4 + PH) % 9][v], lz + (lyv + lx));
-                G[v] = (gzz * gyv[j]) * gxv[v];
-                nw[v] = update<ST>(G[v], q[j][(4 + PH) % 9][v], cc[j][v], lap, pc[j][v], h);
-                lp[v] = lap;
-            }
-            finish_cells<ST, VX, MODE, true>(a, h, z, yj[j], x0, lane_in && yin[j],
-                                       (size_t)z * pp + (size_t)yj[j] * px + x0, nw, lp, cc[j],
-                                       G, inj, bmax);
+            yj[j] = yb + wy + NW * j;
+            yin[j] = FULL || yj[j] < ny;
+            gyv[j] = yin[j] ? a.gy[yj[j]] : 0.0f;
         }
-    };
-    using std::integral_constant;
-#if FD_UNROLL9
-    for (int z = zb; z < ze; z += 9) {
-        plane_step(integral_constant<int, 0>{}, z);
-        if (z + 1 >= ze) break;
-        plane_step(integral_constant<int, 1>{}, z + 1);
-        if (z + 2 >= ze) break;
-        plane_step(integral_constant<int, 2>{}, z + 2);
-        if (z + 3 >= ze) break;
-        plane_step(integral_constant<int, 3>{}, z + 3);
-        if (z + 4 >= ze) break;
-        plane_step(integral_constant<int, 4>{}, z + 4);
-        if (z + 5 >= ze) break;
-        plane_step(integral_constant<int, 5>{}, z + 5);
-        if (z + 6 >= ze) break;
-        plane_step(integral_constant<int, 6>{}, z + 6);
-        if (z + 7 >= ze) break;
-        plane_step(integral_constant<int, 7>{}, z + 7);
-        if (z + 8 >= ze) break;
-        plane_step(integral_constant<int, 8>{}, z + 8);
-    }
-#else
-    for (int z = zb; z < ze; ++z) {
-        plane_step(integral_constant<int, 0>{}, z);
-#pragma unroll
+        float gxv[VX];
+    #pragma unroll
+        for (int v = 0; v < VX; ++v) gxv[v] = (FULL || x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
+
+        // y-halo rows handled by this thread: k = wy + NW hh, hh < 8 / NW.
+        int hy[HH], hyslot[HH];
+        bool hyv[HH];
+    #pragma unroll
+        for (int hh = 0; hh < HH; ++hh) {
+            const int k = wy + NW * hh;
+            const int ly = k < 4 ? k - 4 : TY + k - 4;
+            hy[hh] = yb + ly;
+            hyv[hh] = FULL || (hy[hh] >= 0 && hy[hh] < ny && lane_in);
+            hyslot[hh] = (ly + 4) * LW + 4 + lane * VX;
+        }
+        // x-halo cell handled by this thread (threads < 8 TY).
+        const bool hxl = threadIdx.x < 8 * TY;
+        int hxx = 0, hxy = 0, hxslot = 0;
+        if (hxl) {
+            const int lr = threadIdx.x >> 3, ci = threadIdx.x & 7;
+            hxx = ci < 4 ? xb - 4 + ci : xb + TX + ci - 4;
+            hxy = yb + lr;
+            hxslot = (lr + 4) * LW + (ci < 4 ? ci : TX + ci);
+        }
+        const bool hxv = hxl && hxx >= 0 && hxx < nx && hxy < ny;
+
+        // Loads return raw packs (zero outside the grid); values are decoded
+        // where they are consumed, so a prefetch never waits for its own load.
+        using PT = Pack<T, VX>;
+        using PF = Pack<float, VX>;
+        auto ld3 = [&](const T *base, int z, int y) -> PT {
+            PT p{};
+            if (z >= 0 && z < nz && (FULL || (y < ny && lane_in)))
+                p = ldp<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
+            return p;
+        };
+        auto ld3nt = [&](const T *base, int z, int y) -> PT {
+            PT p{};
+            if (z < nz && (FULL || (y < ny && lane_in)))
+                p = ldp_stream<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
+            return p;
+        };
+        auto ldc3 = [&](int z, int y) -> PF {
+            PF p{};
+            if (z < nz && (FULL || (y < ny && lane_in)))
+                p = ldp_stream<float, VX>(a.c + (size_t)z * pp + (size_t)y * px + x0);
+            return p;
+        };
+        auto ldhy = [&](int z, int hh) -> PT {
+            PT p{};
+            if ((FULL || hyv[hh]) && z < nz) p = ldp<T, VX>(cur + (size_t)z * pp + (size_t)hy[hh] * px + x0);
+            return p;
+        };
+        auto ldhx = [&](int z) -> T {
+            return (hxv && z < nz) ? cur[(size_t)z * pp + (size_t)hxy * px + hxx] : (T)0;
+        };
+
+        float q[RY][9][VX];
+    #pragma unroll
         for (int j = 0; j < RY; ++j)
-#pragma unroll
-            for (int k = 0; k < 8; ++k)
-#pragma unroll
-                for (int v = 0; v < VX; ++v) q[j][k][v] = q[j][k + 1][v];
-    }
-#endif
+    #pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const PT p = ld3(cur, zb - 4 + k, yj[j]);
+    #pragma unroll
+                for (int v = 0; v < VX; ++v) q[j][k][v] = decode_raw<ST>(p.v[v]);
+            }
+        PT la[RY], pv[RY], yh[HH];
+        PF cv[RY];
+    #pragma unroll
+        for (int j = 0; j < RY; ++j) {
+            la[j] = ld3(cur, zb + 4, yj[j]);
+            pv[j] = ld3nt(prv, zb, yj[j]);
+            cv[j] = ldc3(zb, yj[j]);
+        }
+    #pragma unroll
+        for (int hh = 0; hh < HH; ++hh) yh[hh] = ldhy(zb, hh);
+        T xh = ldhx(zb);
+        float bmax = 0.0f;
+
+        // One plane.  At phase PH, plane z - 4 + k of the register queue sits in
+        // slot (k + PH) mod 9.  With FD_UNROLL9 the plane loop is unrolled 9
+        // times so the queue rotates by renaming; otherwise it runs at phase 0
+        // and the values shift down one slot per plane.
+        auto plane_step = [&](auto phase, int z) {
+            constexpr int PH = decltype(phase)::value;
+            float pc[RY][VX], cc[RY][VX], yhc[HH][VX];
+    #pragma unroll
+            for (int j = 0; j < RY; ++j)
+    #pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    q[j][(8 + PH) % 9][v] = decode_raw<ST>(la[j].v[v]);
+                    pc[j][v] = decode_raw<ST>(pv[j].v[v]);
+                    cc[j][v] = cv[j].v[v];
+                }
+    #pragma unroll
+            for (int hh = 0; hh < HH; ++hh)
+    #pragma unroll
+                for (int v = 0; v < VX; ++v) yhc[hh][v] = decode_raw<ST>(yh[hh].v[v]);
+            const float xhc = decode_raw<ST>(xh);
+            if (z + 1 < ze) {
+    #pragma unroll
+                for (int j = 0; j < RY; ++j) {
+                    la[j] = ld3(cur, z + 5, yj[j]);
+                    pv[j] = ld3nt(prv, z + 1, yj[j]);
+                    cv[j] = ldc3(z + 1, yj[j]);
+                }
+    #pragma unroll
+                for (int hh = 0; hh < HH; ++hh) yh[hh] = ldhy(z + 1, hh);
+                xh = ldhx(z + 1);
+            }
+            float *P = pl[z & 1];
+    #pragma unroll
+            for (int j = 0; j < RY; ++j)
+    #pragma unroll
+                for (int v = 0; v < VX; ++v) P[(wy + NW * j + 4) * LW + 4 + lane * VX + v] = q[j][(4 + PH) % 9][v];
+    #pragma unroll
+            for (int hh = 0; hh < HH; ++hh)
+    #pragma unroll
+                for (int v = 0; v < VX; ++v) P[hyslot[hh] + v] = yhc[hh][v];
+            if (hxl) P[hxslot] = xhc;
+            __syncthreads();
+            const float gzz = a.gz[z];
+    #pragma unroll
+            for (int j = 0; j < RY; ++j) {
+                float nw[VX], lp[VX], G[VX];
+    #pragma unroll
+                for (int v = 0; v < VX; ++v) {
+                    const int li = (wy + NW * j + 4) * LW + 4 + lane * VX + v;
+                    const float lx = stencil_taps(P[li - 4], P[li - 3], P[li - 2], P[li - 1], P[li + 1],
+                                                  P[li + 2], P[li + 3], P[li + 4]);
+                    const float lyv = stencil_taps(P[li - 4 * LW], P[li - 3 * LW], P[li - 2 * LW],
+                                                   P[li - LW], P[li + LW], P[li + 2 * LW],
+                                                   P[li + 3 * LW], P[li + 4 * LW]);
+                    const float lz = stencil_taps(q[j][(0 + PH) % 9][v], q[j][(1 + PH) % 9][v],
+                                                  q[j][(2 + PH) % 9][v], q[j][(3 + PH) % 9][v],
+                                                  q[j][(5 + PH) % 9][v], q[j][(6 + PH) % 9][v],
+                                                  q[j][(7 + PH) % 9][v], q[j][(8 + PH) % 9][v]);
+                    const float lap = fmaf(3.0f * kA0, q[j][(4 + PH) % 9][v], lz + (lyv + lx));
+                    G[v] = (gzz * gyv[j]) * gxv[v];
+                    nw[v] = update<ST>(G[v], q[j][(4 + PH) % 9][v], cc[j][v], lap, pc[j][v], h);
+                    lp[v] = lap;
+                }
+                finish_cells<ST, VX, MODE, true>(a, h, z, yj[j], x0, lane_in && yin[j],
+                                           (size_t)z * pp + (size_t)yj[j] * px + x0, nw, lp, cc[j],
+                                           G, inj, bmax);
+            }
+        };
+        using std::integral_constant;
+    #if FD_UNROLL9
+        for (int z = zb; z < ze; z += 9) {
+            plane_step(integral_constant<int, 0>{}, z);
+            if (z + 1 >= ze) break;
+            plane_step(integral_constant<int, 1>{}, z + 1);
+            if (z + 2 >= ze) break;
+            plane_step(integral_constant<int, 2>{}, z + 2);
+            if (z + 3 >= ze) break;
+            plane_step(integral_constant<int, 3>{}, z + 3);
+            if (z + 4 >= ze) break;
+            plane_step(integral_constant<int, 4>{}, z + 4);
+            if (z + 5 >= ze) break;
+            plane_step(integral_constant<int, 5>{}, z + 5);
+            if (z + 6 >= ze) break;
+            plane_step(integral_constant<int, 6>{}, z + 6);
+            if (z + 7 >= ze) break;
+            plane_step(integral_constant<int, 7>{}, z + 7);
+            if (z + 8 >= ze) break;
+            plane_step(integral_constant<int, 8>{}, z + 8);
+        }
+    #else
+        for (int z = zb; z < ze; ++z) {
+            plane_step(integral_constant<int, 0>{}, z);
+    #pragma unroll
+            for (int j = 0; j < RY; ++j)
+    #pragma unroll
+                for (int k = 0; k < 8; ++k)
+    #pragma unroll
+                    for (int v = 0; v < VX; ++v) q[j][k][v] = q[j][k + 1][v];
+        }
+    #endif
+        return bmax;
+    };
+    const bool full = FD_FULL_TILES && xb + TX <= nx && yb >= 4 && yb + TY + 4 <= ny;
+    const float bmax = full ? tile(std::true_type{}) : tile(std::false_type{});
     if constexpr (ST != kF32) block_max_to<64 * NW>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax, red);
 }
 
