@@ -505,7 +505,8 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
     #endif
         return bmax;
     };
-    const bool full = FD_FULL_TILES && xb + TX <= nx && yb >= 4 && yb + TY + 4 <= ny;
+    // (measured: a small gain with 16-bit fields, a small loss with FP32)
+    const bool full = FD_FULL_TILES && ST != kF32 && xb + TX <= nx && yb >= 4 && yb + TY + 4 <= ny;
     const float bmax = full ? tile(std::true_type{}) : tile(std::false_type{});
     if constexpr (ST != kF32) block_max_to<64 * NW>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax, red);
 }
