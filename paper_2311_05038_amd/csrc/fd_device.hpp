@@ -47,6 +47,7 @@ struct StepArgs {
     int32_t zc;           // planes (rows in 2D) per block
     int32_t vx;           // cells per lane along x (2D tile width 64 * vx)
     int32_t tiles_x, tiles_y, tiles_z;
+    int32_t resident;     // 3D: blocks resident at once (tile mapping)
     int32_t sz, sy, sx;   // source cell
     float amp;            // dt^2 / h^D
     const float *wavelet; // device, nt samples
@@ -77,6 +78,20 @@ template <typename T, int VX>
 __device__ __forceinline__ void stp(T *p, const Pack<T, VX> &x)
 {
     *reinterpret_cast<Pack<T, VX> *>(p) = x;
+}
+
+// p + e elements with a 32-bit element offset: for a wave-uniform p the
+// address is a scalar base plus a 32-bit lane offset, which the global
+// load/store instructions take directly.
+template <typename T>
+__device__ __forceinline__ T *at(T *p, uint32_t e)
+{
+    return (T *)((char *)p + e * (uint32_t)sizeof(T));
+}
+template <typename T>
+__device__ __forceinline__ const T *at(const T *p, uint32_t e)
+{
+    return (const T *)((const char *)p + e * (uint32_t)sizeof(T));
 }
 
 // Raw integer vector of a given byte size, for the non-temporal builtins.
@@ -148,7 +163,7 @@ __device__ __forceinline__ float f16_bits_scaled(uint16_t q)
 
 // Decode used inside the step kernels, before the power-of-two field scale:
 // FP32 and bfloat16 exactly, binary16 either exactly (hardware conversion)
-// or times 2^-112 (bit move; the step applies kF16Unscale once per cell).
+// or times 2^-112 (bit move; the 2^112 goes into the update's coefficients).
 template <int ST>
 __device__ __forceinline__ float decode_raw(typename Stor<ST>::T q)
 {
@@ -157,7 +172,6 @@ __device__ __forceinline__ float decode_raw(typename Stor<ST>::T q)
     else
         return decode<ST>(q, 1.0f);
 }
-constexpr float kF16Unscale = 5.192296858534828e+33f;  // 2^112
 
 // Round-to-nearest-even encode of x * inv_scale.
 template <int ST>
@@ -174,6 +188,35 @@ __device__ __forceinline__ typename Stor<ST>::T encode(float x, float inv_scale)
     }
 }
 
+// Pairs of FP32 values rounded to nearest even into 16-bit codes with the
+// gfx950 two-value conversions (v_cvt_pk_f16_f32 / v_cvt_pk_bf16_f32); the
+// values arrive already scaled by 2^-e.
+template <int ST, int VX>
+__device__ __forceinline__ void encode_pairs(const float (&x)[VX], uint16_t (&q)[VX])
+{
+    static_assert(VX % 2 == 0 || VX == 1, "pairs");
+    if constexpr (VX == 1) {
+        q[0] = encode<ST>(x[0], 1.0f);
+    } else {
+#pragma unroll
+        for (int v = 0; v < VX; v += 2) {
+            if constexpr (ST == kF16) {
+                typedef _Float16 h2 __attribute__((ext_vector_type(2)));
+                const h2 r = {(_Float16)x[v], (_Float16)x[v + 1]};
+                const uint32_t u = __builtin_bit_cast(uint32_t, r);
+                q[v] = (uint16_t)u;
+                q[v + 1] = (uint16_t)(u >> 16);
+            } else {
+                typedef __bf16 b2 __attribute__((ext_vector_type(2)));
+                const b2 r = {(__bf16)x[v], (__bf16)x[v + 1]};
+                const uint32_t u = __builtin_bit_cast(uint32_t, r);
+                q[v] = (uint16_t)u;
+                q[v + 1] = (uint16_t)(u >> 16);
+            }
+        }
+    }
+}
+
 // 2^e for e in [-126, 127].
 __device__ __forceinline__ float pow2i(int e) { return __uint_as_float((uint32_t)(e + 127) << 23); }
 
@@ -186,9 +229,15 @@ __device__ __forceinline__ int storage_exponent(float m)
     return (int)((__float_as_uint(t) >> 23) & 0xFFu) - 127 - 11;
 }
 
-// Per-launch quantities of the 16-bit storage form.
+// Per-launch quantities of the 16-bit storage form.  The step computes the
+// new field directly in its storage units (value times 2^-en): the decode
+// scales of cur and prev are multiplied by the encode scale 2^-en (and, for
+// binary16 codes decoded by bit move, by 2^112), which is exact for powers
+// of two, so rounding the result to 16 bits needs no further multiply.
 struct HalfCtx {
-    float sc, sp, sn_inv;  // decode scale of cur and prev, encode scale of new
+    float sc, sp;   // 2^(ec - en) [* 2^112], 2^(ep - en) [* 2^112]
+    float sn;       // 2^en: storage units -> value (traces, magnitude)
+    float sn_inv;   // 2^-en: value -> storage units (source term)
 };
 
 // Layout of the 16-bit storage bookkeeping ("meta", in the state buffer):
@@ -211,7 +260,7 @@ __device__ __forceinline__ float level_max(const int32_t *meta, int level)
 template <int ST>
 __device__ __forceinline__ HalfCtx half_prologue(const StepArgs &a, float inj, bool block0)
 {
-    HalfCtx h{1.0f, 1.0f, 1.0f};
+    HalfCtx h{1.0f, 1.0f, 1.0f, 1.0f};
     if constexpr (ST != kF32) {
         const int ic = (int)(a.n & 3), ip = (int)((a.n + 3) & 3);
         const int in = (int)((a.n + 1) & 3), iz = (int)((a.n + 2) & 3);
@@ -219,8 +268,12 @@ __device__ __forceinline__ HalfCtx half_prologue(const StepArgs &a, float inj, b
         float m = fmaxf(level_max(a.meta, ic), level_max(a.meta, ip));
         m = fmaxf(m, fabsf(inj));
         const int en = storage_exponent(m);
-        h.sc = pow2i(ec);
-        h.sp = pow2i(ep);
+        // ec - en and ep - en stay within a few units (the magnitude changes
+        // by a bounded factor per step); the clamp only keeps 2^k finite.
+        const int bias = (ST == kF16 && FD_F16_BITS) ? 112 : 0;
+        h.sc = pow2i(min(ec - en + bias, 127));
+        h.sp = pow2i(min(ep - en + bias, 127));
+        h.sn = pow2i(en);
         h.sn_inv = pow2i(-en);
         if (block0) {
             if (threadIdx.x == 0) a.meta[in] = en;
@@ -275,6 +328,26 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks)
     const int per = nblocks >> 3;
     if (bid < (per << 3)) return (bid & 7) * per + (bid >> 3);
     return bid;
+}
+
+#ifndef FD_XCD_ROUNDS
+#define FD_XCD_ROUNDS 1
+#endif
+
+// 3D variant.  Blocks run in rounds of `resident` (the blocks the device
+// holds at once; later blocks start, in index order, as earlier ones end).
+// Within each round, XCD k gets the k-th eighth of the round's tiles
+// (t = chunk * cols + column, so consecutive tiles are x/y neighbours at one
+// depth), which keeps the blocks sharing an L2 neighbours whatever the
+// chunk length.  A ragged tail (fewer than 8 blocks) keeps its index.
+__device__ __forceinline__ int xcd_tile3d(int bid, int nblocks, int resident)
+{
+    if (!FD_XCD_ROUNDS || resident < 8) return xcd_tile(bid, nblocks);
+    const int base = bid / resident * resident;
+    const int m8 = min(resident, nblocks - base) & ~7;
+    const int w = bid - base;
+    if (w >= m8) return bid;
+    return base + (w & 7) * (m8 >> 3) + (w >> 3);
 }
 
 }  // namespace fdk

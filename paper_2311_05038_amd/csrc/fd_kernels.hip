@@ -23,6 +23,28 @@
 #ifndef FD_UNROLL9
 #define FD_UNROLL9 0
 #endif
+#ifndef FD_OFF32_F32
+#define FD_OFF32_F32 0
+#endif
+// Memory-op ordering of the step loops for FP32 fields (16-bit fields always
+// use all three): store each row/plane one step late, prefetch
+// unconditionally, and carry the z sponge factor with the prefetch.  With
+// them the 16-bit steps overlap the next plane's loads with the compute
+// (768x768x512 BF16 649 -> 566 us); the FP32 steps measured slower with
+// them (512^3 366 -> 387 us), so they are off there.
+#ifndef FD_DEFER32
+#define FD_DEFER32 0
+#endif
+#ifndef FD_UNCOND32
+#define FD_UNCOND32 0
+#endif
+#ifndef FD_GZPF32
+#define FD_GZPF32 0
+#endif
+// 1: 16-bit 3D steps use the reordered (fewer-instruction) FP32 arithmetic.
+#ifndef FD_H16_ARITH
+#define FD_H16_ARITH 1
+#endif
 // 1: tiles wholly inside the grid take a path without per-lane load tests.
 #ifndef FD_FULL_TILES
 #define FD_FULL_TILES 1
@@ -33,11 +55,46 @@ namespace fdk {
 // --------------------------------------------------------------------------
 // Epilogue shared by 2D and 3D: receivers, source, padding, store.
 // --------------------------------------------------------------------------
-template <int ST, int VX, int MODE, bool STREAM>
+// A row's outgoing values, stored one plane (row) later: the stores are then
+// issued right before the next prefetch instead of right after the compute.
+// Vector loads and stores share one completion counter and a wait for a
+// load also waits for every store issued after it, so a store issued late
+// would make the next plane's wait for its prefetched data wait for that
+// store's round trip as well.
+template <typename T, int VX>
+struct Outgoing {
+    Pack<T, VX> o;
+    Pack<float, VX> L;  // L(cur), kFwdLap only
+    T *dst;
+    float *ldst;
+    bool ok;
+};
+
+template <typename T, int VX, int MODE, bool STREAM>
+__device__ __forceinline__ void flush(Outgoing<T, VX> &out)
+{
+    if (out.ok) {
+        if constexpr (STREAM)
+            stp_stream<T, VX>(out.dst, out.o);
+        else
+            stp<T, VX>(out.dst, out.o);
+        if constexpr (MODE == kFwdLap) stp<float, VX>(out.ldst, out.L);
+    }
+    out.ok = false;
+}
+
+// nw holds the new values (FP32 fields) or the new values in storage units
+// (16-bit fields: value = h.sn * nw).  FULL: every cell of the lane lies
+// inside the grid (x < nx), so no padding mask is needed.  The adjoint
+// step (which reads lap and g here) stores at once; the forward steps leave
+// their stores in `out`.
+template <int ST, int VX, int MODE, bool STREAM, bool FULL>
 __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h, int z, int y,
-                                             int x0, bool store_ok, size_t off, float (&nw)[VX],
+                                             int x0, bool store_ok, size_t row, uint32_t eo,
+                                             float (&nw)[VX],
                                              const float (&lp)[VX], const float (&cc)[VX],
-                                             const float (&G)[VX], float inj, float &bmax)
+                                             const float (&G)[VX], float inj, float &bmax,
+                                             Outgoing<typename Stor<ST>::T, VX> &out)
 {
     using T = typename Stor<ST>::T;
     // Receiver box membership of this row (z, y).
@@ -62,42 +119,49 @@ __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h
 #pragma unroll
             for (int v = 0; v < VX; ++v) {
                 const int xr = x0 + v - a.rec.x0;
-                if (x0 + v < a.nx && xr >= 0 && xr % a.rec.dx == 0 && xr / a.rec.dx < a.rec.nx)
-                    a.trace_row[(size_t)rrow * a.rec.nx + xr / a.rec.dx] = nw[v];
+                if (x0 + v < a.nx && xr >= 0 && xr % a.rec.dx == 0 && xr / a.rec.dx < a.rec.nx) {
+                    if constexpr (ST == kF32)
+                        a.trace_row[(size_t)rrow * a.rec.nx + xr / a.rec.dx] = nw[v];
+                    else
+                        a.trace_row[(size_t)rrow * a.rec.nx + xr / a.rec.dx] = nw[v] * h.sn;
+                }
             }
         }
         if (z == a.sz && y == a.sy) {
+            const float inj_s = ST == kF32 ? inj : inj * h.sn_inv;
 #pragma unroll
             for (int v = 0; v < VX; ++v)
-                if (x0 + v == a.sx) nw[v] += inj;
+                if (x0 + v == a.sx) nw[v] += inj_s;
         }
     }
 #pragma unroll
     for (int v = 0; v < VX; ++v) {
-        if (x0 + v >= a.nx) nw[v] = 0.0f;
+        if (!FULL && x0 + v >= a.nx) nw[v] = 0.0f;
         if constexpr (ST != kF32) bmax = fmaxf(bmax, fabsf(nw[v]));
     }
-    if (!store_ok) return;
     T *prv = (T *)a.prev;
-    Pack<T, VX> o;
+    if constexpr (ST == kF32) {
 #pragma unroll
-    for (int v = 0; v < VX; ++v) o.v[v] = encode<ST>(nw[v], h.sn_inv);
-    if constexpr (STREAM)
-        stp_stream<T, VX>(prv + off, o);
-    else
-        stp<T, VX>(prv + off, o);
+        for (int v = 0; v < VX; ++v) out.o.v[v] = nw[v];
+    } else {
+        encode_pairs<ST, VX>(nw, out.o.v);
+    }
+    out.dst = at(prv + row, eo);
+    out.ok = store_ok;
     if constexpr (MODE == kFwdLap) {
-        Pack<float, VX> L;
 #pragma unroll
-        for (int v = 0; v < VX; ++v) L.v[v] = (x0 + v < a.nx) ? lp[v] : 0.0f;
-        stp<float, VX>(a.lap + off, L);
+        for (int v = 0; v < VX; ++v) out.L.v[v] = (FULL || x0 + v < a.nx) ? lp[v] : 0.0f;
+        out.ldst = at(a.lap + row, eo);
     }
     if constexpr (MODE == kAdj) {
-        const Pack<float, VX> lw = ldp<float, VX>(a.lap + off);
-        Pack<double, VX> gg = ldp<double, VX>(a.g + off);
+        flush<T, VX, MODE, STREAM>(out);
+        if (store_ok) {
+            const Pack<float, VX> lw = ldp<float, VX>(at(a.lap + row, eo));
+            Pack<double, VX> gg = ldp<double, VX>(at(a.g + row, eo));
 #pragma unroll
-        for (int v = 0; v < VX; ++v) gg.v[v] = fma((double)nw[v], (double)lw.v[v], gg.v[v]);
-        stp<double, VX>(a.g + off, gg);
+            for (int v = 0; v < VX; ++v) gg.v[v] = fma((double)nw[v], (double)lw.v[v], gg.v[v]);
+            stp<double, VX>(at(a.g + row, eo), gg);
+        }
     }
 }
 
@@ -116,23 +180,19 @@ __device__ __forceinline__ float leapfrog(float G, float ctr, float c, float lap
     return fmaf(G, fmaf(c, lap, 2.0f * ctr), -(G * G) * prev);
 }
 
-// The same update on 16-bit fields read without their power-of-two scales
-// (P = sc q, Pold = sp qp, and L q computed from the unscaled q): the scales
-// go into the coefficients, (G sc)(2 q + c L q) - (G^2 sp) qp, which is
-// exactly the scaled arithmetic since multiplying by 2^k does not round.
+// The same update on 16-bit fields read as raw codes q (P = 2^ec q, Pold =
+// 2^ep qp, and L q computed from the raw q), producing the new field in its
+// storage units 2^-en: (G sc)(2 q + c L q) - (G^2 sp) qp with sc = 2^(ec-en)
+// and sp = 2^(ep-en) (times 2^112 for bit-moved binary16 codes).  This is the
+// scaled arithmetic exactly, since multiplying by 2^k does not round.
 template <int ST>
 __device__ __forceinline__ float update(float G, float ctr, float c, float lap, float prev,
                                         const HalfCtx &h)
 {
-    if constexpr (ST == kF32) {
+    if constexpr (ST == kF32)
         return leapfrog(G, ctr, c, lap, prev);
-    } else if constexpr (ST == kF16 && FD_F16_BITS) {
-        // operands carry 2^-112 (decode_raw); restore it before the scales
-        return fmaf(G * h.sc, fmaf(c, lap, 2.0f * ctr) * kF16Unscale,
-                    -((G * G) * h.sp) * (prev * kF16Unscale));
-    } else {
+    else
         return fmaf(G * h.sc, fmaf(c, lap, 2.0f * ctr), -((G * G) * h.sp) * prev);
-    }
 }
 
 // --------------------------------------------------------------------------
@@ -202,6 +262,13 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
     PT la = ld_cur(zb + 4), pv = ld_prev(zb);
     PF cv = ld_c(zb);
     T hv = ld_halo(zb);
+    // the row's sponge factor travels with the prefetch: a load issued after
+    // it and waited for in the same row would also wait for the prefetch
+    constexpr bool DEFER = ST != kF32 || FD_DEFER32, UNCOND = ST != kF32 || FD_UNCOND32;
+    constexpr bool GZPF = ST != kF32 || FD_GZPF32;
+    float gn = a.gz[zb];
+    Outgoing<T, VX> out;
+    out.ok = false;
 
     for (int z = zb; z < ze; ++z) {
         float pc[VX], cc[VX];
@@ -212,18 +279,29 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
             cc[v] = cv.v[v];
         }
         const float hc = decode_raw<ST>(hv);
-        if (z + 1 < ze) {
+        const float gzp = gn;
+        // the previous row's stores go out after the wait for this row's
+        // data and just before the next prefetch
+        if constexpr (DEFER) {
+            __builtin_amdgcn_sched_barrier(0);
+            flush<T, VX, MODE, false>(out);
+        }
+        // unconditional (rows past the chunk are in bounds or read as zero):
+        // a skipped prefetch would make the compiler copy the previous
+        // registers, and the copy waits for every outstanding memory access
+        if (UNCOND || z + 1 < ze) {
             la = ld_cur(z + 5);
             pv = ld_prev(z + 1);
             cv = ld_c(z + 1);
             hv = ld_halo(z + 1);
+            if constexpr (GZPF) gn = z + 1 < nz ? a.gz[z + 1] : 0.0f;
         }
         float *rw = row[z & 1];
 #pragma unroll
         for (int v = 0; v < VX; ++v) rw[4 + lane * VX + v] = q[4][v];
         if (hlane) rw[hslot] = hc;
         __syncthreads();
-        const float gzz = a.gz[z];
+        const float gzz = GZPF ? gzp : a.gz[z];
         float nw[VX], lp[VX], G[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
@@ -237,13 +315,15 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
             nw[v] = update<ST>(G[v], q[4][v], cc[v], lap, pc[v], h);
             lp[v] = lap;
         }
-        finish_cells<ST, VX, MODE, false>(a, h, z, 0, x0, lane_in, (size_t)z * px + x0, nw, lp, cc, G,
-                                   inj, bmax);
+        finish_cells<ST, VX, MODE, false, false>(a, h, z, 0, x0, lane_in, (size_t)z * px, (uint32_t)x0, nw,
+                                                 lp, cc, G, inj, bmax, out);
+        if constexpr (!DEFER) flush<T, VX, MODE, false>(out);
 #pragma unroll
         for (int k = 0; k < 8; ++k)
 #pragma unroll
             for (int v = 0; v < VX; ++v) q[k][v] = q[k + 1][v];
     }
+    flush<T, VX, MODE, false>(out);
 }
 
 template <int ST, int VX, int MODE>
@@ -259,7 +339,8 @@ __global__ __launch_bounds__(64) void k_step2d(StepArgs a)
     const HalfCtx h = half_prologue<ST>(a, inj, blockIdx.x == 0);
     float bmax = 0.0f;
     step2d_tile<ST, VX, MODE>(a, tx, tz, row, h, inj, bmax);
-    if constexpr (ST != kF32) block_max_to<64>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax, nullptr);
+    if constexpr (ST != kF32)
+        block_max_to<64>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax * h.sn, nullptr);
 }
 
 // Batched 2D FP32 forward step: block b belongs to the item whose tile range
@@ -275,7 +356,7 @@ __global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
     const int lt = t - b.begin[i];
     const int tx = lt % a.tiles_x, tz = lt / a.tiles_x;
     const float inj = (a.n + 1 < a.nt) ? a.amp * a.wavelet[a.n + 1] : 0.0f;
-    const HalfCtx h{1.0f, 1.0f, 1.0f};
+    const HalfCtx h{1.0f, 1.0f, 1.0f, 1.0f};
     float bmax = 0.0f;
     step2d_tile<kF32, VX, kFwd>(a, tx, tz, row, h, inj, bmax);
 }
@@ -283,17 +364,24 @@ __global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
 // --------------------------------------------------------------------------
 // 3D
 // --------------------------------------------------------------------------
-template <int ST, int VX, int RY, int NW, int MODE>
-__global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
+#ifdef FD_MINB16
+#define FD_3D_BOUNDS __launch_bounds__(64 * NW, ST == kF32 ? 1 : FD_MINB16)
+#else
+#define FD_3D_BOUNDS __launch_bounds__(64 * NW)
+#endif
+template <int ST, int VX, int RY, int NW, int MODE, int PFD>
+__global__ FD_3D_BOUNDS void k_step3d(StepArgs a)
 {
     using T = typename Stor<ST>::T;
     static_assert(NW == 2 || NW == 4 || NW == 8, "waves per block");
+    static_assert(PFD == 1 || PFD == 2, "planes prefetched");
     constexpr int TX = 64 * VX, TY = NW * RY, LW = TX + 8, LH = TY + 8, HH = 8 / NW;
     __shared__ float pl[2][LH * LW];
     __shared__ float red[NW];
+    // wave index read as a wave-uniform value, so row tests become scalar branches
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
     const int nb = a.tiles_x * a.tiles_y * a.tiles_z;
-    const int t = xcd_tile(blockIdx.x, nb);
+    const int t = xcd_tile3d(blockIdx.x, nb, a.resident);
     const int tx = t % a.tiles_x;
     const int t2 = t / a.tiles_x;
     const int ty = t2 % a.tiles_y, tz = t2 / a.tiles_y;
@@ -324,9 +412,12 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
             yin[j] = FULL || yj[j] < ny;
             gyv[j] = yin[j] ? a.gy[yj[j]] : 0.0f;
         }
-        float gxv[VX];
+        float gxv[VX], gxv2[VX];
     #pragma unroll
-        for (int v = 0; v < VX; ++v) gxv[v] = (FULL || x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
+        for (int v = 0; v < VX; ++v) {
+            gxv[v] = (FULL || x0 + v < nx) ? a.gx[x0 + v] : 0.0f;
+            gxv2[v] = gxv[v] * gxv[v];
+        }
 
         // y-halo rows handled by this thread: k = wy + NW hh, hh < 8 / NW.
         int hy[HH], hyslot[HH];
@@ -350,35 +441,55 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
         }
         const bool hxv = hxl && hxx >= 0 && hxx < nx && hxy < ny;
 
+        // Element offsets within a plane (32-bit: a plane holds < 2^29
+        // cells): each access is a wave-uniform plane pointer plus a lane
+        // offset, which keeps the address arithmetic scalar.  (FP32 fields,
+        // bandwidth-bound, measured faster with plain 64-bit addresses.)
+        constexpr bool OFF32 = ST != kF32 || FD_OFF32_F32;
+        constexpr bool DEFER = ST != kF32 || FD_DEFER32, UNCOND = ST != kF32 || FD_UNCOND32;
+        constexpr bool GZPF = ST != kF32 || FD_GZPF32;
+        auto addr = [&](auto *base, int z, uint32_t e, int y, int x) {
+            if constexpr (OFF32)
+                return at(base + (size_t)z * pp, e);
+            else
+                return base + (size_t)z * pp + (size_t)y * px + x;
+        };
+        uint32_t eo[RY], eohy[HH];
+    #pragma unroll
+        for (int j = 0; j < RY; ++j) eo[j] = (uint32_t)(yj[j] * a.px + x0);
+    #pragma unroll
+        for (int hh = 0; hh < HH; ++hh) eohy[hh] = (FULL || hyv[hh]) ? (uint32_t)(hy[hh] * a.px + x0) : 0u;
+        const uint32_t eohx = hxv ? (uint32_t)(hxy * a.px + hxx) : 0u;
+
         // Loads return raw packs (zero outside the grid); values are decoded
         // where they are consumed, so a prefetch never waits for its own load.
         using PT = Pack<T, VX>;
         using PF = Pack<float, VX>;
-        auto ld3 = [&](const T *base, int z, int y) -> PT {
+        auto ld3 = [&](const T *base, int z, int j) -> PT {
             PT p{};
-            if (z >= 0 && z < nz && (FULL || (y < ny && lane_in)))
-                p = ldp<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
+            if (z >= 0 && z < nz && (FULL || (yin[j] && lane_in)))
+                p = ldp<T, VX>(addr(base, z, eo[j], yj[j], x0));
             return p;
         };
-        auto ld3nt = [&](const T *base, int z, int y) -> PT {
+        auto ld3nt = [&](const T *base, int z, int j) -> PT {
             PT p{};
-            if (z < nz && (FULL || (y < ny && lane_in)))
-                p = ldp_stream<T, VX>(base + (size_t)z * pp + (size_t)y * px + x0);
+            if (z < nz && (FULL || (yin[j] && lane_in)))
+                p = ldp_stream<T, VX>(addr(base, z, eo[j], yj[j], x0));
             return p;
         };
-        auto ldc3 = [&](int z, int y) -> PF {
+        auto ldc3 = [&](int z, int j) -> PF {
             PF p{};
-            if (z < nz && (FULL || (y < ny && lane_in)))
-                p = ldp_stream<float, VX>(a.c + (size_t)z * pp + (size_t)y * px + x0);
+            if (z < nz && (FULL || (yin[j] && lane_in)))
+                p = ldp_stream<float, VX>(addr(a.c, z, eo[j], yj[j], x0));
             return p;
         };
         auto ldhy = [&](int z, int hh) -> PT {
             PT p{};
-            if ((FULL || hyv[hh]) && z < nz) p = ldp<T, VX>(cur + (size_t)z * pp + (size_t)hy[hh] * px + x0);
+            if ((FULL || hyv[hh]) && z < nz) p = ldp<T, VX>(addr(cur, z, eohy[hh], hy[hh], x0));
             return p;
         };
         auto ldhx = [&](int z) -> T {
-            return (hxv && z < nz) ? cur[(size_t)z * pp + (size_t)hxy * px + hxx] : (T)0;
+            return (hxv && z < nz) ? *addr(cur, z, eohx, hxy, hxx) : (T)0;
         };
 
         float q[RY][9][VX];
@@ -386,22 +497,40 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
         for (int j = 0; j < RY; ++j)
     #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const PT p = ld3(cur, zb - 4 + k, yj[j]);
+                const PT p = ld3(cur, zb - 4 + k, j);
     #pragma unroll
                 for (int v = 0; v < VX; ++v) q[j][k][v] = decode_raw<ST>(p.v[v]);
             }
-        PT la[RY], pv[RY], yh[HH];
-        PF cv[RY];
+        // Prefetched raw data of one plane zz: cur at zz + 4 (the queue's
+        // next entry), prev and c at zz, and the halo cells of cur at zz.
+        // PFD planes are in flight ahead of the one being computed.
+        struct Ahead {
+            PT la[RY], pv[RY], yh[HH];
+            PF cv[RY];
+            T xh;
+            float gz;   // sponge factor of plane zz (loaded here, not after
+                        // the prefetch, so waiting for it never waits for
+                        // the next plane's loads)
+        };
+        auto fetch = [&](int zz, Ahead &r) {
     #pragma unroll
-        for (int j = 0; j < RY; ++j) {
-            la[j] = ld3(cur, zb + 4, yj[j]);
-            pv[j] = ld3nt(prv, zb, yj[j]);
-            cv[j] = ldc3(zb, yj[j]);
-        }
+            for (int j = 0; j < RY; ++j) {
+                r.la[j] = ld3(cur, zz + 4, j);
+                r.pv[j] = ld3nt(prv, zz, j);
+                r.cv[j] = ldc3(zz, j);
+            }
     #pragma unroll
-        for (int hh = 0; hh < HH; ++hh) yh[hh] = ldhy(zb, hh);
-        T xh = ldhx(zb);
+            for (int hh = 0; hh < HH; ++hh) r.yh[hh] = ldhy(zz, hh);
+            r.xh = ldhx(zz);
+            if constexpr (GZPF) r.gz = zz < nz ? a.gz[zz] : 0.0f;
+        };
+        Ahead ah[PFD];
+    #pragma unroll
+        for (int d = 0; d < PFD; ++d) fetch(zb + d, ah[d]);
         float bmax = 0.0f;
+        Outgoing<T, VX> out[RY];
+    #pragma unroll
+        for (int j = 0; j < RY; ++j) out[j].ok = false;
 
         // One plane.  At phase PH, plane z - 4 + k of the register queue sits in
         // slot (k + PH) mod 9.  With FD_UNROLL9 the plane loop is unrolled 9
@@ -414,26 +543,30 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
             for (int j = 0; j < RY; ++j)
     #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    q[j][(8 + PH) % 9][v] = decode_raw<ST>(la[j].v[v]);
-                    pc[j][v] = decode_raw<ST>(pv[j].v[v]);
-                    cc[j][v] = cv[j].v[v];
+                    q[j][(8 + PH) % 9][v] = decode_raw<ST>(ah[0].la[j].v[v]);
+                    pc[j][v] = decode_raw<ST>(ah[0].pv[j].v[v]);
+                    cc[j][v] = ah[0].cv[j].v[v];
                 }
     #pragma unroll
             for (int hh = 0; hh < HH; ++hh)
     #pragma unroll
-                for (int v = 0; v < VX; ++v) yhc[hh][v] = decode_raw<ST>(yh[hh].v[v]);
-            const float xhc = decode_raw<ST>(xh);
-            if (z + 1 < ze) {
+                for (int v = 0; v < VX; ++v) yhc[hh][v] = decode_raw<ST>(ah[0].yh[hh].v[v]);
+            const float xhc = decode_raw<ST>(ah[0].xh);
+            const float gzp = ah[0].gz;
+            // the previous plane's stores go out after the wait for this
+            // plane's data and just before the next prefetch
+            if constexpr (DEFER) {
+                __builtin_amdgcn_sched_barrier(0);
     #pragma unroll
-                for (int j = 0; j < RY; ++j) {
-                    la[j] = ld3(cur, z + 5, yj[j]);
-                    pv[j] = ld3nt(prv, z + 1, yj[j]);
-                    cv[j] = ldc3(z + 1, yj[j]);
-                }
-    #pragma unroll
-                for (int hh = 0; hh < HH; ++hh) yh[hh] = ldhy(z + 1, hh);
-                xh = ldhx(z + 1);
+                for (int j = 0; j < RY; ++j) flush<T, VX, MODE, true>(out[j]);
             }
+    #pragma unroll
+            for (int d = 0; d + 1 < PFD; ++d) ah[d] = ah[d + 1];
+            // unconditional (planes past the chunk are in bounds or read
+            // as zero): a skipped fetch would make the compiler keep and
+            // copy the previous plane's registers, and copying them waits
+            // for every outstanding memory operation
+            if (UNCOND || z + PFD < ze) fetch(z + PFD, ah[PFD - 1]);
             float *P = pl[z & 1];
     #pragma unroll
             for (int j = 0; j < RY; ++j)
@@ -445,10 +578,34 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                 for (int v = 0; v < VX; ++v) P[hyslot[hh] + v] = yhc[hh][v];
             if (hxl) P[hxslot] = xhc;
             __syncthreads();
-            const float gzz = a.gz[z];
+            const float gzz = GZPF ? gzp : a.gz[z];
     #pragma unroll
             for (int j = 0; j < RY; ++j) {
                 float nw[VX], lp[VX], G[VX];
+                if constexpr (ST != kF32 && FD_H16_ARITH) {
+                    // 16-bit fields (VALU-bound): taps summed over the three
+                    // axes before weighting, and the sponge factor's square
+                    // taken per lane and per row, which saves instructions at
+                    // a different FP32 rounding order.
+                    const float gr = gzz * gyv[j];
+                    const float r1 = gr * h.sc, r2 = (gr * gr) * h.sp;
+    #pragma unroll
+                    for (int v = 0; v < VX; ++v) {
+                        const int li = (wy + NW * j + 4) * LW + 4 + lane * VX + v;
+                        const float(&qq)[9][VX] = q[j];
+                        float sk[4];
+    #pragma unroll
+                        for (int k = 1; k <= 4; ++k)
+                            sk[k - 1] = ((P[li - k] + P[li + k]) + (P[li - k * LW] + P[li + k * LW])) +
+                                        (qq[(4 - k + PH) % 9][v] + qq[(4 + k + PH) % 9][v]);
+                        const float ctr = qq[(4 + PH) % 9][v];
+                        const float lap = fmaf(3.0f * kA0, ctr,
+                                               fmaf(kA4, sk[3], fmaf(kA3, sk[2], fmaf(kA2, sk[1], kA1 * sk[0]))));
+                        G[v] = 0.0f;
+                        nw[v] = fmaf(gxv[v] * r1, fmaf(cc[j][v], lap, 2.0f * ctr), -(gxv2[v] * r2) * pc[j][v]);
+                        lp[v] = lap;
+                    }
+                } else {
     #pragma unroll
                 for (int v = 0; v < VX; ++v) {
                     const int li = (wy + NW * j + 4) * LW + 4 + lane * VX + v;
@@ -466,9 +623,16 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                     nw[v] = update<ST>(G[v], q[j][(4 + PH) % 9][v], cc[j][v], lap, pc[j][v], h);
                     lp[v] = lap;
                 }
-                finish_cells<ST, VX, MODE, true>(a, h, z, yj[j], x0, lane_in && yin[j],
-                                           (size_t)z * pp + (size_t)yj[j] * px + x0, nw, lp, cc[j],
-                                           G, inj, bmax);
+                }
+                if constexpr (OFF32)
+                    finish_cells<ST, VX, MODE, true, FULL>(a, h, z, yj[j], x0, lane_in && yin[j],
+                                                           (size_t)z * pp, eo[j], nw, lp, cc[j], G, inj, bmax,
+                                                           out[j]);
+                else
+                    finish_cells<ST, VX, MODE, true, FULL>(a, h, z, yj[j], x0, lane_in && yin[j],
+                                                           (size_t)z * pp + (size_t)yj[j] * px, (uint32_t)x0, nw,
+                                                           lp, cc[j], G, inj, bmax, out[j]);
+                if constexpr (!DEFER) flush<T, VX, MODE, true>(out[j]);
             }
         };
         using std::integral_constant;
@@ -503,12 +667,15 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                     for (int v = 0; v < VX; ++v) q[j][k][v] = q[j][k + 1][v];
         }
     #endif
+    #pragma unroll
+        for (int j = 0; j < RY; ++j) flush<T, VX, MODE, true>(out[j]);
         return bmax;
     };
     // (measured: a small gain with 16-bit fields, a small loss with FP32)
     const bool full = FD_FULL_TILES && ST != kF32 && xb + TX <= nx && yb >= 4 && yb + TY + 4 <= ny;
     const float bmax = full ? tile(std::true_type{}) : tile(std::false_type{});
-    if constexpr (ST != kF32) block_max_to<64 * NW>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax, red);
+    if constexpr (ST != kF32)
+        block_max_to<64 * NW>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax * h.sn, red);
 }
 
 // --------------------------------------------------------------------------
@@ -734,7 +901,14 @@ hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, i
 #ifndef FD_3D_NW16
 #define FD_3D_NW16 4
 #endif
+#ifndef FD_3D_PF32
+#define FD_3D_PF32 1
+#endif
+#ifndef FD_3D_PF16
+#define FD_3D_PF16 1
+#endif
 constexpr int k3dVX32 = FD_3D_VX32, k3dRY32 = FD_3D_RY32;   // FP32 fields
+constexpr int k3dPF32 = FD_3D_PF32, k3dPF16 = FD_3D_PF16;   // planes prefetched
 constexpr int k3dVX16 = FD_3D_VX16, k3dRY16 = FD_3D_RY16;   // 16-bit fields
 constexpr int kBatchVX = 2;
 
@@ -751,15 +925,15 @@ static int64_t resident_blocks_3d(int storage)
         if (e == hipSuccess) {
             if (storage == kF32)
                 e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF32, k3dVX32, k3dRY32, FD_3D_NW32, kFwd>),
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF32, k3dVX32, k3dRY32, FD_3D_NW32, kFwd, k3dPF32>),
                     64 * FD_3D_NW32, 0);
             else if (storage == kF16)
                 e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd>),
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd, k3dPF16>),
                     64 * FD_3D_NW16, 0);
             else
                 e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kBF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd>),
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kBF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd, k3dPF16>),
                     64 * FD_3D_NW16, 0);
         }
         (void)hipGetLastError();
@@ -799,11 +973,14 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
 #else
         // Planes per block: a block streams zc planes after priming 8 halo
         // planes, and blocks run in ceil(blocks / resident) rounds, so the
-        // time goes as ceil(blocks / resident) * (zc + 8).  Ties go to the
+        // time goes as ceil(blocks / resident) * (zc + 8).  The column is cut
+        // into k equal chunks (zc = ceil(nz / k) >= 16); ties go to the
         // longer chunk (less halo traffic).
         const int64_t cols = (int64_t)a.tiles_x * a.tiles_y;
         const int64_t resident = resident_blocks_3d(storage);
+        a.resident = (int32_t)std::min<int64_t>(resident, 1 << 30);
         int64_t best = -1;
+#ifdef FD_PLAN_POW2
         for (int zc = 256; zc >= 16; zc >>= 1) {
             const int64_t nb = cols * ((a.nz + zc - 1) / zc);
             const int64_t cost = ((nb + resident - 1) / resident) * (std::min(zc, a.nz) + 8);
@@ -812,6 +989,17 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
                 a.zc = zc;
             }
         }
+#else
+        for (int k = 1; k <= std::max(1, a.nz / 16); ++k) {
+            const int zc = (a.nz + k - 1) / k;
+            const int64_t nb = cols * ((a.nz + zc - 1) / zc);
+            const int64_t cost = ((nb + resident - 1) / resident) * (int64_t)(zc + 8);
+            if (best < 0 || cost < best) {
+                best = cost;
+                a.zc = zc;
+            }
+        }
+#endif
 #endif
         a.tiles_z = (a.nz + a.zc - 1) / a.zc;
     }
@@ -821,10 +1009,10 @@ template <int ST, int MODE>
 static void launch3d(const StepArgs &a, int nb, hipStream_t s)
 {
     if constexpr (ST == kF32)
-        hipLaunchKernelGGL((k_step3d<ST, k3dVX32, k3dRY32, FD_3D_NW32, MODE>), dim3(nb),
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX32, k3dRY32, FD_3D_NW32, MODE, k3dPF32>), dim3(nb),
                            dim3(64 * FD_3D_NW32), 0, s, a);
     else
-        hipLaunchKernelGGL((k_step3d<ST, k3dVX16, k3dRY16, FD_3D_NW16, MODE>), dim3(nb),
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX16, k3dRY16, FD_3D_NW16, MODE, k3dPF16>), dim3(nb),
                            dim3(64 * FD_3D_NW16), 0, s, a);
 }
 
