@@ -14,6 +14,7 @@ on the same GPU) add keys to the same line:
   half     16-bit field storage on the 768x768x512 precision grid, 2000 steps
   adjoint  the 8-shot velocity gradient on the 1024^2 model, 2000 steps
   serve    a Poisson stream of 2D shots, continuous batching vs sequential
+  routines the step as one kernel per routine vs the fused step
 """
 from __future__ import annotations
 
@@ -198,6 +199,49 @@ def serve_leg(n_requests: int = 60, seed: int = 50):
     return res
 
 
+def routines_leg(nsteps: int = 50):
+    """The step as one kernel per routine (fd_step_routines: derivative
+    fields materialised, then the time update and the source addition)
+    against the fused step, on the 512^3 headline model and on a 2048x4096
+    2D grid: microseconds per step and algorithmic GB/s (52 B per cell in 3D,
+    40 B in 2D, against 16 B fused).  Per-kernel times are in the committed
+    rocprofv3 kernel trace."""
+    import torch
+    import fd_inputs as fi
+    from helpers import setup
+    out = {}
+    for name, p, bpc in (("3d", fi.layered3d(nt=nsteps + 5), 52),
+                         ("2d", fi.surface2d(2048, 4096, nsteps + 5, seed=7), 40)):
+        model, state, shot = setup(p)
+        work = torch.empty(model.sizes.routines_work, dtype=torch.uint8, device="cuda")
+        res = {}
+        for form in ("routines", "fused"):
+            state.begin(shot)
+            step = ((lambda n: state.step_routines(shot, n, work)) if form == "routines"
+                    else (lambda n: state.step(shot, n)))
+            for n in range(5):
+                step(n)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            torch.cuda.synchronize()
+            e0.record()
+            for n in range(5, 5 + nsteps):
+                step(n)
+            e1.record()
+            torch.cuda.synchronize()
+            us = e0.elapsed_time(e1) * 1e3 / nsteps
+            b = bpc if form == "routines" else 16
+            res[form] = dict(us_per_step=round(us, 2), bytes_per_cell=b,
+                             alg_gbs=round(b * p.ncells / (us * 1e-6) / 1e9, 1))
+        res["fused_speedup"] = round(res["routines"]["us_per_step"] / res["fused"]["us_per_step"], 3)
+        res["grid"] = "x".join(str(d) for d in p.shape)
+        out[name] = res
+        log(f"[bench] routines leg {name}: {res}")
+        del model, state, shot, work
+        torch.cuda.empty_cache()
+    return out
+
+
 def traffic_from_profiles(kernel_tag: str):
     """HBM bytes per launch from the committed rocprofv3 counter summary, or
     None when the kernel source changed after the counters were taken."""
@@ -241,8 +285,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--probe-only", action="store_true",
                     help="only the 1 GiB copy probe (counter calibration)")
-    ap.add_argument("--legs", default="half,adjoint,serve",
-                    help="comma list of extra legs (half, adjoint, serve) or 'none'")
+    ap.add_argument("--legs", default="half,adjoint,serve,routines",
+                    help="comma list of extra legs (half, adjoint, serve, routines) or 'none'")
     ap.add_argument("--serve-requests", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -270,6 +314,8 @@ def main():
         extra["adjoint"] = adjoint_leg()
     if "serve" in legs:
         extra["serving"] = serve_leg(args.serve_requests)
+    if "routines" in legs:
+        extra["routines"] = routines_leg()
     cpu = None if args.no_cpu else cpu_baseline()
     traffic = traffic_from_profiles("k_step3d_f32_layered3d_512")
     out = {

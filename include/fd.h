@@ -110,6 +110,7 @@ typedef struct {
     size_t state;        /* fd_create_state's buffer (two time levels) */
     size_t checkpoints;  /* fd_run_shot's checkpoint buffer for (nt, ckpt_every) */
     size_t adjoint_work; /* fd_adjoint_gradient's work buffer for ckpt_every */
+    size_t routines_work; /* fd_step_routines' work buffer (ndim FP32 fields) */
 } fd_sizes;
 
 typedef struct fd_model fd_model;
@@ -205,6 +206,20 @@ typedef struct {
  * (host) to the next step of each item.  Results equal fd_step on each
  * item alone, bit for bit.  2D, FP32 storage, count <= FD_BATCH_MAX. */
 fd_status fd_step_batch(fd_batch_item *items, int32_t count, int32_t nsteps, void *stream);
+
+/* Time step n computed as Listing 3 lays it out, one kernel per routine:
+ * fd_pzz (the z taps of the second difference of P into a Pzz field),
+ * fd_pxx (x taps into Pxx), in 3D the same along y (Pyy), fd_time (Pnew =
+ * G (2 P + c (a0 D P + Pzz + Pyy + Pxx)) - G^2 Pold over Pold, receivers
+ * sampled into trace_row as in fd_step), add_source (the source addition of
+ * step n+1 into Pnew), then the rotation.  The derivative fields live in
+ * `work` (device, >= fd_sizes.routines_work bytes, contents undefined on
+ * return).  Same preconditions and the same results as fd_step, bit for
+ * bit; it moves 40 (2D) or 52 (3D) bytes per cell instead of 16.  It exists
+ * to measure the routines one by one against the fused step.  FP32 storage
+ * only (FD_ERR_UNSUPPORTED otherwise). */
+fd_status fd_step_routines(const fd_model *model, fd_state *state, const fd_shot *shot, int64_t n,
+                           float *trace_row, void *work, size_t work_bytes, void *stream);
 
 /* Message for the last non-OK status on this thread ("" if none). */
 const char *fd_last_error(void);

@@ -202,6 +202,16 @@ class State:
                      _stream_handle(stream))
         self.next = n + 1
 
+    def step_routines(self, shot: Shot, n: int, work: torch.Tensor,
+                      trace_row: Optional[torch.Tensor] = None, stream=None) -> None:
+        """Step n as one kernel per routine (fd_step_routines); `work` is a
+        device byte buffer of at least Model.sizes.routines_work bytes."""
+        _abi.fd_step_routines(self.model.handle, self.handle, shot._c, n,
+                              trace_row.data_ptr() if trace_row is not None else None,
+                              work.data_ptr(), work.numel() * work.element_size(),
+                              _stream_handle(stream))
+        self.next = n + 1
+
     def wavefield(self, which: int = 0, out: Optional[torch.Tensor] = None,
                   stream=None) -> torch.Tensor:
         if out is None:

@@ -46,7 +46,8 @@ class fd_shot(ctypes.Structure):
 
 class fd_sizes(ctypes.Structure):
     _fields_ = [("model", ctypes.c_size_t), ("state", ctypes.c_size_t),
-                ("checkpoints", ctypes.c_size_t), ("adjoint_work", ctypes.c_size_t)]
+                ("checkpoints", ctypes.c_size_t), ("adjoint_work", ctypes.c_size_t),
+                ("routines_work", ctypes.c_size_t)]
 
 
 class fd_batch_item(ctypes.Structure):
@@ -78,6 +79,7 @@ SIGNATURES = [
     ("fd_get_wavefield", ctypes.c_int, [_P, _I32, _P, _P]),
     ("fd_set_wavefield", ctypes.c_int, [_P, _I32, _P, _P]),
     ("fd_step_batch", ctypes.c_int, [ctypes.POINTER(fd_batch_item), _I32, _I32, _P]),
+    ("fd_step_routines", ctypes.c_int, [_P, _P, ctypes.POINTER(fd_shot), _I64, _P, _P, _SZ, _P]),
     ("fd_last_error", ctypes.c_char_p, []),
     ("fd_version", ctypes.c_char_p, []),
 ]
@@ -149,6 +151,12 @@ def fd_begin_shot(model: int, state: int, shot: fd_shot, stream: int) -> None:
 
 def fd_step(model: int, state: int, shot: fd_shot, n: int, trace_row_ptr, stream: int) -> None:
     check(lib().fd_step(model, state, ctypes.byref(shot), n, trace_row_ptr, stream))
+
+
+def fd_step_routines(model: int, state: int, shot: fd_shot, n: int, trace_row_ptr, work_ptr: int,
+                     work_bytes: int, stream: int) -> None:
+    check(lib().fd_step_routines(model, state, ctypes.byref(shot), n, trace_row_ptr, work_ptr,
+                                 work_bytes, stream))
 
 
 def fd_run_shot(model: int, state: int, shot: fd_shot, traces_ptr, ckpt_ptr, ckpt_bytes: int,

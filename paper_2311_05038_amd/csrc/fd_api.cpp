@@ -116,6 +116,9 @@ fd_status check_grid(const fd_grid *g)
         return fail(FD_ERR_INVALID_ARG, "unknown storage kind %d", g->storage);
     const double cells = (double)g->nz * (double)g->ny * (double)((g->nx + 63) / 64 * 64);
     if (cells > 4.0e9) return fail(FD_ERR_INVALID_ARG, "grid too large");
+    // the 3D kernels address a plane with 32-bit byte offsets
+    if ((double)g->ny * (double)((g->nx + 63) / 64 * 64) >= 1073741824.0)
+        return fail(FD_ERR_INVALID_ARG, "an x-y plane must hold fewer than 2^30 cells");
     return FD_OK;
 }
 
@@ -247,6 +250,7 @@ fd_status fd_query_bytes(const fd_grid *grid, int64_t nt, int32_t ckpt_every, fd
     out->state = L.state_bytes;
     out->checkpoints = (nt > 0 && ckpt_every > 0) ? (size_t)n_ckpt(nt, ckpt_every) * ckpt_slot_bytes(L) : 0;
     out->adjoint_work = ckpt_every > 0 ? adjoint_work_bytes(L, ckpt_every) : 0;
+    out->routines_work = (size_t)L.ndim * L.f32field;
     return ok();
 }
 
@@ -516,6 +520,38 @@ fd_status fd_set_wavefield(fd_state *state, int32_t which, const float *in, void
     hipError_t e = fdk::launch_set_field(L.storage, in, state->buf[lvl & 1], L.nz * L.ny,
                                          (int32_t)L.nx, L.px, state->meta, (int32_t)(lvl & 3), s);
     if (e != hipSuccess) return hip_fail(e, "fd_set_wavefield");
+    return ok();
+}
+
+fd_status fd_step_routines(const fd_model *model, fd_state *state, const fd_shot *shot, int64_t n,
+                           float *trace_row, void *work, size_t work_bytes, void *stream)
+{
+    if (!model || !state) return fail(FD_ERR_INVALID_ARG, "NULL model or state");
+    if (state->m != model) return fail(FD_ERR_INVALID_ARG, "state was created for another model");
+    fd_status st = check_shot(model, shot);
+    if (st != FD_OK) return st;
+    const Layout &L = model->L;
+    if (L.storage != FD_F32) return fail(FD_ERR_UNSUPPORTED, "the routine-per-kernel step is built for FP32 fields only");
+    if (!work) return fail(FD_ERR_INVALID_ARG, "work is NULL");
+    if (work_bytes < (size_t)L.ndim * L.f32field)
+        return fail(FD_ERR_INVALID_ARG, "work holds %zu bytes, %zu needed", work_bytes,
+                    (size_t)L.ndim * L.f32field);
+    if (state->next < 0) return fail(FD_ERR_INVALID_ARG, "fd_begin_shot has not been called");
+    if (n != state->next) return fail(FD_ERR_INVALID_ARG, "step %lld requested, next step is %lld",
+                                      (long long)n, (long long)state->next);
+    if (n >= shot->nt) return fail(FD_ERR_INVALID_ARG, "step %lld beyond the shot's %lld steps",
+                                   (long long)n, (long long)shot->nt);
+    StepArgs a = base_args(model, shot);
+    a.cur = state->buf[n & 1];
+    a.prev = state->buf[(n + 1) & 1];
+    a.n = n;
+    a.trace_row = nrec_of(shot) > 0 ? trace_row : nullptr;
+    char *w = (char *)work;
+    float *dzz = (float *)w, *dxx = (float *)(w + L.f32field);
+    float *dyy = L.ndim == 3 ? (float *)(w + 2 * L.f32field) : nullptr;
+    hipError_t e = fdk::launch_routines(a, L.ndim, dzz, dxx, dyy, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "routine kernels launch");
+    state->next = n + 1;
     return ok();
 }
 

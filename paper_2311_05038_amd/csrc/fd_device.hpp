@@ -21,6 +21,21 @@ constexpr float kA2 = (float)(-1.0 / 5.0);
 constexpr float kA3 = (float)(8.0 / 315.0);
 constexpr float kA4 = (float)(-1.0 / 560.0);
 
+// sum_k a_k (u_{-k} + u_{+k}), k = 1..4.  The library is built with
+// -ffp-contract=off; every fused multiply-add is written out, so all kernel
+// variants round identically.
+__device__ __forceinline__ float stencil_taps(float m4, float m3, float m2, float m1, float p1,
+                                              float p2, float p3, float p4)
+{
+    return fmaf(kA4, m4 + p4, fmaf(kA3, m3 + p3, fmaf(kA2, m2 + p2, kA1 * (m1 + p1))));
+}
+
+// new = G (2 cur + c lap) - G^2 prev
+__device__ __forceinline__ float leapfrog(float G, float ctr, float c, float lap, float prev)
+{
+    return fmaf(G, fmaf(c, lap, 2.0f * ctr), -(G * G) * prev);
+}
+
 enum Mode : int {
     kFwd = 0,     // forward step
     kFwdLap = 1,  // forward step that also stores L(cur) (adjoint recompute)

@@ -165,20 +165,6 @@ __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h
     }
 }
 
-// sum_k a_k (u_{-k} + u_{+k}), k = 1..4.  The library is built with
-// -ffp-contract=off; every fused multiply-add is written out, so all kernel
-// variants round identically.
-__device__ __forceinline__ float stencil_taps(float m4, float m3, float m2, float m1, float p1,
-                                              float p2, float p3, float p4)
-{
-    return fmaf(kA4, m4 + p4, fmaf(kA3, m3 + p3, fmaf(kA2, m2 + p2, kA1 * (m1 + p1))));
-}
-
-// new = G (2 cur + c lap) - G^2 prev
-__device__ __forceinline__ float leapfrog(float G, float ctr, float c, float lap, float prev)
-{
-    return fmaf(G, fmaf(c, lap, 2.0f * ctr), -(G * G) * prev);
-}
 
 // The same update on 16-bit fields read as raw codes q (P = 2^ec q, Pold =
 // 2^ep qp, and L q computed from the raw q), producing the new field in its

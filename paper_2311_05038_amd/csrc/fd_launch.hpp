@@ -24,6 +24,10 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched);
 
 hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t s);
 hipError_t launch_step_batch2d(Batch2D &b, hipStream_t s);
+// The step as separate routine kernels (derivative fields dzz, dxx and, in
+// 3D, dyy materialised in HBM); FP32 fields only.
+hipError_t launch_routines(const StepArgs &a, int ndim, float *dzz, float *dxx, float *dyy,
+                           hipStream_t s);
 hipError_t launch_fill_u32(void *p, size_t nwords, uint32_t val, hipStream_t s);
 hipError_t launch_model_c(const float *v, float *c, int64_t nrows, int32_t nx, int32_t px,
                           double r, uint32_t *scratch, hipStream_t s);
