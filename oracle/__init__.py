@@ -16,6 +16,10 @@ Parity status of each function (pins live in tests/test_oracle_*.py):
                 adjoint dot-product test and an absorption test
   adjoint       pinned: dot-product test against the tangent-linear model and
                 central finite differences
+  image         pinned: dot-product test against the NumPy twin's
+                tangent-linear model of the scatterer perturbation
+                L -> L + diag(m), and central finite differences of the
+                twin's forward map in m
   forward_half  pinned: conversions bit-exact against numpy float16 and torch
                 bfloat16; the FP32 arithmetic against the NumPy twin's
                 emulation
@@ -73,6 +77,8 @@ def lib():
         L.or_forward.restype = ctypes.c_int
         L.or_adjoint.argtypes = [P, P, P, i64, i64, i64, P, P, P, P]
         L.or_adjoint.restype = ctypes.c_int
+        L.or_image.argtypes = [P, P, P, i64, i64, i64, P, P, P]
+        L.or_image.restype = ctypes.c_int
         L.or_forward_half.argtypes = [P, ctypes.c_int, P, P, i64, i64, i64, P, P, P, P, P]
         L.or_forward_half.restype = ctypes.c_int
         L.or_encode_array.argtypes = [ctypes.c_int, P, P, i64]
@@ -169,6 +175,24 @@ def adjoint(grid: OrGrid, v: np.ndarray, wavelet: np.ndarray, nt: int, src, rec_
     if rc != 0:
         raise MemoryError("oracle adjoint: allocation failed")
     return gv, gc
+
+
+def image(grid: OrGrid, v: np.ndarray, wavelet: np.ndarray, nt: int, src, rec_index,
+          resid: np.ndarray) -> np.ndarray:
+    """Zero-lag correlation image sum_k z^k w^{k-1} of the source wavefield
+    and the z-form receiver wavefield driven by resid (dJ/dm for L -> L +
+    diag(m))."""
+    v = np.ascontiguousarray(v, dtype=np.float32)
+    wavelet = np.ascontiguousarray(wavelet, dtype=np.float32)
+    rec = np.ascontiguousarray(rec_index, dtype=np.int64)
+    resid = np.ascontiguousarray(resid, dtype=np.float64)
+    assert resid.shape == (nt, rec.size)
+    img = np.empty(v.shape, dtype=np.float64)
+    rc = lib().or_image(ctypes.byref(grid), _p(v), _p(wavelet), nt, _src_linear(grid, src),
+                        rec.size, _p(rec), _p(resid), _p(img))
+    if rc != 0:
+        raise MemoryError("oracle image: allocation failed")
+    return img
 
 
 def forward_half(grid: OrGrid, storage: int, v: np.ndarray, wavelet: np.ndarray, nt: int,

@@ -259,6 +259,69 @@ int or_adjoint(const or_grid *g, const float *v, const float *wavelet, int64_t n
     return rc;
 }
 
+/*
+ * Imaging condition (reverse-time migration of one shot).  The source
+ * wavefield w^n (the field after the source addition of step n) is
+ * correlated at zero lag with the receiver wavefield z^k, the z-form
+ * adjoint field of or_adjoint driven by resid (the recorded data, or any
+ * dJ/dtraces):
+ *   image = sum_{k=1..nt} z^k * w^{k-1}.
+ * It is dJ/dm for the spatial operator L -> L + diag(m) at m = 0 (a point
+ * scatterer: the scheme becomes y = G (2 w + c (L w + m w)) - G^2 w_old), by
+ * the same argument as dJ/dc with (L w) replaced by w.  Stores the whole
+ * forward history (nt * N doubles).  image is overwritten.
+ */
+int or_image(const or_grid *g, const float *v, const float *wavelet, int64_t nt, int64_t src,
+             int64_t nrec, const int64_t *rec, const double *resid, double *image)
+{
+    const int64_t N = g->nz * g->ny * g->nx;
+    double *hist = malloc(sizeof(double) * N * nt);
+    double *c = malloc(sizeof(double) * N), *G = malloc(sizeof(double) * N);
+    double *prev = calloc(N, sizeof(double)), *cur = calloc(N, sizeof(double));
+    double *nw = malloc(sizeof(double) * N), *lap = malloc(sizeof(double) * N);
+    double *z1 = calloc(N, sizeof(double)), *z2 = calloc(N, sizeof(double));
+    double *zk = malloc(sizeof(double) * N);
+    if (!hist || !c || !G || !prev || !cur || !nw || !lap || !z1 || !z2 || !zk) {
+        free(hist); free(c); free(G); free(prev); free(cur); free(nw); free(lap);
+        free(z1); free(z2); free(zk);
+        return -1;
+    }
+    or_setup(g, v, c, G);
+    const double amp = source_amp(g);
+    /* forward: keep w^n */
+    for (int64_t n = 0; n < nt; ++n) {
+        if (src >= 0) cur[src] += amp * (double)wavelet[n];
+        memcpy(hist + n * N, cur, sizeof(double) * N);
+        or_laplacian(g, cur, lap);
+        for (int64_t i = 0; i < N; ++i)
+            nw[i] = G[i] * (2.0 * cur[i] + c[i] * lap[i]) - G[i] * G[i] * prev[i];
+        double *t = prev;
+        prev = cur;
+        cur = nw;
+        nw = t;
+    }
+    /* backward: z-form adjoint recursion and the zero-lag correlation */
+    for (int64_t i = 0; i < N; ++i) image[i] = 0.0;
+    for (int64_t k = nt; k >= 1; --k) {
+        or_laplacian(g, z1, lap);
+        for (int64_t i = 0; i < N; ++i)
+            zk[i] = G[i] * (2.0 * z1[i] + c[i] * lap[i]) - G[i] * G[i] * z2[i];
+        for (int64_t r = 0; r < nrec; ++r) {
+            const int64_t i = rec[r];
+            zk[i] += c[i] * G[i] * resid[(k - 1) * nrec + r];
+        }
+        const double *w = hist + (k - 1) * N;
+        for (int64_t i = 0; i < N; ++i) image[i] += zk[i] * w[i];
+        double *t = z2;
+        z2 = z1;
+        z1 = zk;
+        zk = t;
+    }
+    free(hist); free(c); free(G); free(prev); free(cur); free(nw); free(lap);
+    free(z1); free(z2); free(zk);
+    return 0;
+}
+
 /* ------------------------------------------------------------------------
  * 16-bit storage emulation: FP32 arithmetic, fields stored as IEEE binary16
  * or bfloat16 codes q with one power-of-two exponent e per stored field

@@ -154,6 +154,34 @@ class Twin:
             dprev, dcur = dcur, dnew
         return dtr
 
+    def forward_m(self, wavelet, nt, m):
+        """Forward map with the spatial operator L replaced by L + diag(m)
+        (a field of point scatterers): traces only."""
+        G, c = self.G, self.c
+        prev = np.zeros(self.p.shape)
+        cur = np.zeros(self.p.shape)
+        traces = np.zeros((nt, len(self.rec[0])))
+        for n in range(nt):
+            cur = cur.copy()
+            cur[self.src] += self.amp * float(wavelet[n])
+            new = G * (2 * cur + c * (self.L(cur) + m * cur)) - G * G * prev
+            traces[n] = new[self.rec]
+            prev, cur = cur, new
+        return traces
+
+    def tangent_m(self, wavelet, nt, dm):
+        """Tangent-linear model of forward_m at m = 0: d traces for dm."""
+        G, c = self.G, self.c
+        _, _, _, ws = self.forward(wavelet, nt, keep=True)
+        dprev = np.zeros(self.p.shape)
+        dcur = np.zeros(self.p.shape)
+        dtr = np.zeros((nt, len(self.rec[0])))
+        for n in range(nt):
+            dnew = G * (2 * dcur + c * (self.L(dcur) + dm * ws[n])) - G * G * dprev
+            dtr[n] = dnew[self.rec]
+            dprev, dcur = dcur, dnew
+        return dtr
+
     def adjoint_c(self, wavelet, nt, resid):
         """dJ/dc by back-propagation written directly from the forward map
         (ybar recursion, not the z-form used by the C oracle)."""
