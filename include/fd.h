@@ -175,6 +175,22 @@ fd_status fd_adjoint_gradient(const fd_model *model, const fd_shot *shot, const 
                               const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every,
                               void *work, size_t work_bytes, double *grad_v, void *stream);
 
+/* Reverse-time-migration image of one shot (the imaging use the paper
+ * names for this solver, Section 7): accumulates into image (device, dense
+ * FP64, +=) the zero-lag correlation of the source wavefield w^n (the
+ * field after the source addition of step n, recomputed from the
+ * checkpoints) with the receiver wavefield z^k back-propagated from `data`
+ * (device FP32 [nt][nrec]: the recorded traces, or any dJ/dtraces) by the
+ * recursion of fd_adjoint_gradient:
+ *   image += sum_{k=1..nt} z^k * w^{k-1}.
+ * This is dJ/dm for J = <data, traces> with the spatial operator L
+ * replaced by L + diag(m) (a field of point scatterers) at m = 0.  Same
+ * checkpoints, ckpt_every, work buffer (fd_sizes.adjoint_work) and errors
+ * as fd_adjoint_gradient.  FP32 storage only. */
+fd_status fd_rtm_image(const fd_model *model, const fd_shot *shot, const float *data,
+                       const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every, void *work,
+                       size_t work_bytes, double *image, void *stream);
+
 /* Copies P (which = 0) or Pold (which = 1) of the state, decoded to FP32,
  * into `out` (device, dense [nz][ny][nx]).  After k steps P holds the new
  * field of step k-1 plus the source addition of step k (none after the

@@ -172,6 +172,24 @@ class Model:
                                  grad_v.data_ptr(), _stream_handle(stream))
         return grad_v
 
+    def rtm_image(self, shot: Shot, data: torch.Tensor, ckpt: torch.Tensor, ckpt_every: int,
+                  image: torch.Tensor, work: Optional[torch.Tensor] = None,
+                  stream=None) -> torch.Tensor:
+        """fd_rtm_image: image += sum_k z^k w^{k-1} for the receiver field
+        back-propagated from `data` ([nt][nrec] FP32) and the source field
+        recomputed from `ckpt` (saved by run_shot with the same ckpt_every)."""
+        if data.dtype != torch.float32 or not data.is_contiguous():
+            raise ValueError("data must be contiguous FP32")
+        if image.dtype != torch.float64 or image.numel() != self.grid.ncells:
+            raise ValueError("image must be an FP64 tensor of the grid's size")
+        need = self.sizes_for(shot.nt, ckpt_every).adjoint_work
+        if work is None:
+            work = _alloc(need, self.device)
+        _abi.fd_rtm_image(self.handle, shot._c, data.data_ptr(), ckpt.data_ptr(), ckpt.numel(),
+                          ckpt_every, work.data_ptr(), work.numel(), image.data_ptr(),
+                          _stream_handle(stream))
+        return image
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:

@@ -76,6 +76,8 @@ SIGNATURES = [
     ("fd_run_shot", ctypes.c_int, [_P, _P, ctypes.POINTER(fd_shot), _P, _P, _SZ, _I32, _P]),
     ("fd_adjoint_gradient", ctypes.c_int,
      [_P, ctypes.POINTER(fd_shot), _P, _P, _SZ, _I32, _P, _SZ, _P, _P]),
+    ("fd_rtm_image", ctypes.c_int,
+     [_P, ctypes.POINTER(fd_shot), _P, _P, _SZ, _I32, _P, _SZ, _P, _P]),
     ("fd_get_wavefield", ctypes.c_int, [_P, _I32, _P, _P]),
     ("fd_set_wavefield", ctypes.c_int, [_P, _I32, _P, _P]),
     ("fd_step_batch", ctypes.c_int, [ctypes.POINTER(fd_batch_item), _I32, _I32, _P]),
@@ -170,6 +172,13 @@ def fd_adjoint_gradient(model: int, shot: fd_shot, adj_ptr: int, ckpt_ptr: int, 
                         stream: int) -> None:
     check(lib().fd_adjoint_gradient(model, ctypes.byref(shot), adj_ptr, ckpt_ptr, ckpt_bytes,
                                     ckpt_every, work_ptr, work_bytes, grad_v_ptr, stream))
+
+
+def fd_rtm_image(model: int, shot: fd_shot, data_ptr: int, ckpt_ptr: int, ckpt_bytes: int,
+                 ckpt_every: int, work_ptr: int, work_bytes: int, image_ptr: int,
+                 stream: int) -> None:
+    check(lib().fd_rtm_image(model, ctypes.byref(shot), data_ptr, ckpt_ptr, ckpt_bytes,
+                             ckpt_every, work_ptr, work_bytes, image_ptr, stream))
 
 
 def fd_get_wavefield(state: int, which: int, out_ptr: int, stream: int) -> None:

@@ -424,16 +424,24 @@ fd_status fd_run_shot(const fd_model *model, fd_state *state, const fd_shot *sho
     return ok();
 }
 
-fd_status fd_adjoint_gradient(const fd_model *model, const fd_shot *shot, const float *adj,
-                              const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every, void *work,
-                              size_t work_bytes, double *grad_v, void *stream)
+}  // extern "C"
+
+namespace {
+
+// Checkpointed backward pass shared by the gradient and the image: each
+// segment is recomputed storing the history field of every step (L w^n for
+// the gradient, w^n for the image), then the z-form adjoint field is
+// stepped back through the segment accumulating sum_k z^k * hist^{k-1} in
+// FP64.  On success *acc points at that sum (padded, inside `work`).
+fd_status backward_pass(const fd_model *model, const fd_shot *shot, const float *adj,
+                        const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every, void *work,
+                        size_t work_bytes, int hist_mode, hipStream_t s, double **acc)
 {
-    if (!model) return fail(FD_ERR_INVALID_ARG, "NULL model");
     fd_status st = check_shot(model, shot);
     if (st != FD_OK) return st;
     const Layout &L = model->L;
     if (L.storage != FD_F32) return fail(FD_ERR_UNSUPPORTED, "the adjoint needs FP32 storage");
-    if (!adj || !ckpt || !work || !grad_v) return fail(FD_ERR_INVALID_ARG, "NULL adj, ckpt, work or grad_v");
+    if (!adj || !ckpt || !work) return fail(FD_ERR_INVALID_ARG, "NULL adj, ckpt or work");
     if (ckpt_every < 1) return fail(FD_ERR_INVALID_ARG, "ckpt_every must be >= 1");
     const int64_t nt = shot->nt;
     const int64_t nseg = n_ckpt(nt, ckpt_every);
@@ -443,10 +451,9 @@ fd_status fd_adjoint_gradient(const fd_model *model, const fd_shot *shot, const 
         return fail(FD_ERR_INVALID_ARG, "adjoint work buffer too small (%zu < %zu bytes)", work_bytes,
                     adjoint_work_bytes(L, ckpt_every));
     if ((uintptr_t)work % kAlign) return fail(FD_ERR_INVALID_ARG, "work buffer must be 256-byte aligned");
-    hipStream_t s = (hipStream_t)stream;
     char *w = (char *)work;
     void *fw[2] = {w, w + L.f32field};
-    float *lap = (float *)(w + 2 * L.f32field);
+    float *hist = (float *)(w + 2 * L.f32field);
     char *zb = w + 2 * L.f32field + (size_t)ckpt_every * L.f32field;
     void *zf[2] = {zb, zb + L.f32field};
     double *g = (double *)(zb + 2 * L.f32field);
@@ -468,8 +475,8 @@ fd_status fd_adjoint_gradient(const fd_model *model, const fd_shot *shot, const 
             a.prev = fw[(n + 1) & 1];
             a.n = n;
             a.trace_row = nullptr;
-            a.lap = (float *)((char *)lap + (size_t)(n - n0) * L.f32field);
-            e = fdk::launch_step(a, L.ndim, L.storage, fdk::kFwdLap, s);
+            a.lap = (float *)((char *)hist + (size_t)(n - n0) * L.f32field);
+            e = fdk::launch_step(a, L.ndim, L.storage, hist_mode, s);
             if (e != hipSuccess) return hip_fail(e, "recompute step");
         }
         for (int64_t k = n1; k >= n0 + 1; --k) {
@@ -478,16 +485,53 @@ fd_status fd_adjoint_gradient(const fd_model *model, const fd_shot *shot, const 
             a.prev = zf[k & 1];
             a.n = k;
             a.nt = 0;  // no source in the adjoint recursion
-            a.lap = (float *)((char *)lap + (size_t)(k - 1 - n0) * L.f32field);
+            a.lap = (float *)((char *)hist + (size_t)(k - 1 - n0) * L.f32field);
             a.resid_row = nrec > 0 ? adj + (size_t)(k - 1) * (size_t)nrec : nullptr;
             a.g = g;
             e = fdk::launch_step(a, L.ndim, L.storage, fdk::kAdj, s);
             if (e != hipSuccess) return hip_fail(e, "adjoint step");
         }
     }
-    e = fdk::launch_grad_finish(g, model->c, grad_v, L.nz * L.ny, (int32_t)L.nx, L.px,
-                                2.0 * model->grid.dt / model->grid.dh, s);
+    *acc = g;
+    return FD_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+fd_status fd_adjoint_gradient(const fd_model *model, const fd_shot *shot, const float *adj,
+                              const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every, void *work,
+                              size_t work_bytes, double *grad_v, void *stream)
+{
+    if (!model) return fail(FD_ERR_INVALID_ARG, "NULL model");
+    if (!grad_v) return fail(FD_ERR_INVALID_ARG, "NULL grad_v");
+    hipStream_t s = (hipStream_t)stream;
+    double *g = nullptr;
+    fd_status st = backward_pass(model, shot, adj, ckpt, ckpt_bytes, ckpt_every, work, work_bytes,
+                                 fdk::kFwdLap, s, &g);
+    if (st != FD_OK) return st;
+    const Layout &L = model->L;
+    hipError_t e = fdk::launch_grad_finish(g, model->c, grad_v, L.nz * L.ny, (int32_t)L.nx, L.px,
+                                           2.0 * model->grid.dt / model->grid.dh, s);
     if (e != hipSuccess) return hip_fail(e, "gradient finish");
+    return ok();
+}
+
+fd_status fd_rtm_image(const fd_model *model, const fd_shot *shot, const float *data,
+                       const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every, void *work,
+                       size_t work_bytes, double *image, void *stream)
+{
+    if (!model) return fail(FD_ERR_INVALID_ARG, "NULL model");
+    if (!image) return fail(FD_ERR_INVALID_ARG, "NULL image");
+    hipStream_t s = (hipStream_t)stream;
+    double *g = nullptr;
+    fd_status st = backward_pass(model, shot, data, ckpt, ckpt_bytes, ckpt_every, work, work_bytes,
+                                 fdk::kFwdKeep, s, &g);
+    if (st != FD_OK) return st;
+    const Layout &L = model->L;
+    hipError_t e = fdk::launch_image_finish(g, image, L.nz * L.ny, (int32_t)L.nx, L.px, s);
+    if (e != hipSuccess) return hip_fail(e, "image finish");
     return ok();
 }
 

@@ -39,8 +39,12 @@ __device__ __forceinline__ float leapfrog(float G, float ctr, float c, float lap
 enum Mode : int {
     kFwd = 0,     // forward step
     kFwdLap = 1,  // forward step that also stores L(cur) (adjoint recompute)
-    kAdj = 2      // adjoint step: receiver injection of c G r, g += new * L(w)
+    kAdj = 2,     // adjoint step: receiver injection of c G r, g += new * hist
+    kFwdKeep = 3  // forward step that also stores cur itself (imaging recompute)
 };
+
+// Forward modes that write a per-step history field (StepArgs::lap).
+constexpr bool stores_history(int mode) { return mode == kFwdLap || mode == kFwdKeep; }
 
 enum StorageKind : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
 
@@ -70,7 +74,7 @@ struct StepArgs {
     RecBox rec;
     float *trace_row;     // nrec floats of row n, or null
     int32_t *meta;        // 16-bit storage: e[4] exponents then max|.|[4] bits
-    float *lap;           // kFwdLap: out;  kAdj: in (L w^{k-1}), padded FP32
+    float *lap;           // kFwdLap/kFwdKeep: out (L cur / cur);  kAdj: in, padded FP32
     const float *resid_row;  // kAdj: dJ/dtraces row k-1 (nrec), or null
     double *g;            // kAdj: FP64 accumulator, padded
 };

@@ -64,7 +64,7 @@ namespace fdk {
 template <typename T, int VX>
 struct Outgoing {
     Pack<T, VX> o;
-    Pack<float, VX> L;  // L(cur), kFwdLap only
+    Pack<float, VX> L;  // history value (L cur or cur), history modes only
     T *dst;
     float *ldst;
     bool ok;
@@ -78,7 +78,7 @@ __device__ __forceinline__ void flush(Outgoing<T, VX> &out)
             stp_stream<T, VX>(out.dst, out.o);
         else
             stp<T, VX>(out.dst, out.o);
-        if constexpr (MODE == kFwdLap) stp<float, VX>(out.ldst, out.L);
+        if constexpr (stores_history(MODE)) stp<float, VX>(out.ldst, out.L);
     }
     out.ok = false;
 }
@@ -148,7 +148,7 @@ __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h
     }
     out.dst = at(prv + row, eo);
     out.ok = store_ok;
-    if constexpr (MODE == kFwdLap) {
+    if constexpr (stores_history(MODE)) {
 #pragma unroll
         for (int v = 0; v < VX; ++v) out.L.v[v] = (FULL || x0 + v < a.nx) ? lp[v] : 0.0f;
         out.ldst = at(a.lap + row, eo);
@@ -299,7 +299,7 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
             const float lap = fmaf(2.0f * kA0, q[4][v], lz + lx);
             G[v] = gzz * gxv[v];
             nw[v] = update<ST>(G[v], q[4][v], cc[v], lap, pc[v], h);
-            lp[v] = lap;
+            lp[v] = MODE == kFwdKeep ? q[4][v] : lap;
         }
         finish_cells<ST, VX, MODE, false, false>(a, h, z, 0, x0, lane_in, (size_t)z * px, (uint32_t)x0, nw,
                                                  lp, cc, G, inj, bmax, out);
@@ -607,7 +607,7 @@ __global__ FD_3D_BOUNDS void k_step3d(StepArgs a)
                     const float lap = fmaf(3.0f * kA0, q[j][(4 + PH) % 9][v], lz + (lyv + lx));
                     G[v] = (gzz * gyv[j]) * gxv[v];
                     nw[v] = update<ST>(G[v], q[j][(4 + PH) % 9][v], cc[j][v], lap, pc[j][v], h);
-                    lp[v] = lap;
+                    lp[v] = MODE == kFwdKeep ? q[j][(4 + PH) % 9][v] : lap;
                 }
                 }
                 if constexpr (OFF32)
@@ -788,6 +788,19 @@ __global__ void k_grad_finish(const double *__restrict__ g, const float *__restr
     }
 }
 
+// image += the accumulated zero-lag correlation (padded -> dense).
+__global__ void k_image_finish(const double *__restrict__ g, double *__restrict__ image,
+                               int64_t nrows, int32_t nx, int32_t px)
+{
+    const size_t total = (size_t)nrows * nx;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        const size_t rw = i / (size_t)nx, x = i - rw * (size_t)nx;
+        image[i] += g[rw * (size_t)px + x];
+    }
+}
+
 // --------------------------------------------------------------------------
 // Host launchers
 // --------------------------------------------------------------------------
@@ -856,6 +869,14 @@ hipError_t launch_set_field(int storage, const float *in, void *buf, int64_t nro
     case kF16: hipLaunchKernelGGL(k_set_field<kF16>, g, b, 0, s, in, buf, nrows, nx, px, meta, slot); break;
     default: hipLaunchKernelGGL(k_set_field<kBF16>, g, b, 0, s, in, buf, nrows, nx, px, meta, slot); break;
     }
+    return hipGetLastError();
+}
+
+hipError_t launch_image_finish(const double *g, double *image, int64_t nrows, int32_t nx,
+                               int32_t px, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_image_finish, dim3(grid_blocks((size_t)nrows * nx, 256)), dim3(256), 0, s,
+                       g, image, nrows, nx, px);
     return hipGetLastError();
 }
 
@@ -1009,6 +1030,7 @@ static void launch2d(const StepArgs &a, int storage, int mode, int nb, hipStream
     if (storage == kF32) {
         if (mode == kFwd) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwd>), g, b, 0, s, a);
         else if (mode == kFwdLap) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwdLap>), g, b, 0, s, a);
+        else if (mode == kFwdKeep) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwdKeep>), g, b, 0, s, a);
         else hipLaunchKernelGGL((k_step2d<kF32, VX, kAdj>), g, b, 0, s, a);
     } else if (storage == kF16) {
         hipLaunchKernelGGL((k_step2d<kF16, VX, kFwd>), g, b, 0, s, a);
@@ -1028,6 +1050,7 @@ hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t 
         if (storage == kF32) {
             if (mode == kFwd) launch3d<kF32, kFwd>(a, nb, s);
             else if (mode == kFwdLap) launch3d<kF32, kFwdLap>(a, nb, s);
+            else if (mode == kFwdKeep) launch3d<kF32, kFwdKeep>(a, nb, s);
             else launch3d<kF32, kAdj>(a, nb, s);
         } else if (storage == kF16) {
             launch3d<kF16, kFwd>(a, nb, s);

@@ -37,6 +37,8 @@ hipError_t launch_get_field(int storage, const void *buf, float *out, int64_t nr
                             int32_t px, const int32_t *meta, int32_t level_slot, hipStream_t s);
 hipError_t launch_set_field(int storage, const float *in, void *buf, int64_t nrows, int32_t nx,
                             int32_t px, int32_t *meta, int32_t slot, hipStream_t s);
+hipError_t launch_image_finish(const double *g, double *image, int64_t nrows, int32_t nx,
+                               int32_t px, hipStream_t s);
 hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, int64_t nrows,
                               int32_t nx, int32_t px, double two_dt_over_h, hipStream_t s);
 
