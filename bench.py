@@ -154,22 +154,25 @@ def adjoint_leg(nt: int = 2000, every: int = 50):
     cells = p.ncells * p.nt * len(shots)
     # reverse-time-migration image of the 8 observed shots in the start model
     # (forward with checkpoints, then recompute + back-propagation per shot)
-    m0 = fd.Model(grid, v0t)
-    s0 = m0.new_state()
-    ck = m0.checkpoint_buffer(p.nt, every)
-    work = torch.empty(m0.sizes_for(p.nt, every).adjoint_work, dtype=torch.uint8, device="cuda")
-    img = torch.zeros(p.ncells, dtype=torch.float64, device="cuda")
+    from paper_2311_05038_amd.autograd import rtm_image
+    rtm_image(v0t, grid, shots[:1], obs[:1], every)     # warm-up
     torch.cuda.synchronize()
     t = time.perf_counter()
-    for i, s in enumerate(shots):
-        m0.run_shot(s0, s, ckpt=ck, ckpt_every=every)
-        m0.rtm_image(s, obs[i], ck, every, img, work=work)
+    img = rtm_image(v0t, grid, shots, obs, every)
     torch.cuda.synchronize()
     sec_img = time.perf_counter() - t
+    # the same gradient with the shots one after another on one stream
+    l2_misfit_gradient(v0t, grid, shots, obs, every, lanes=1)
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    l2_misfit_gradient(v0t, grid, shots, obs, every, lanes=1)
+    torch.cuda.synchronize()
+    sec_1 = time.perf_counter() - t
     out = dict(workload="adjoint2d 1024^2, 8 shots, nt=2000, K=50", seconds_per_gradient=round(sec, 3),
                forward_equiv_mcell_per_s=round(3 * cells / sec / 1e6, 1), misfit=J,
                grad_norm=float(g.norm()), seconds_per_rtm_image=round(sec_img, 3),
-               image_norm=float(img.norm()))
+               image_norm=float(img.norm()), shot_lanes=4,
+               seconds_per_gradient_one_lane=round(sec_1, 3))
     log(f"[bench] adjoint leg: {out}")
     return out
 

@@ -65,6 +65,31 @@ def test_gradient_against_finite_differences_of_gpu_forward():
     assert abs(fdv - an) <= 1e-2 * abs(an)
 
 
+def test_shot_lanes_equal_one_lane():
+    """Shots on concurrent streams (per-lane FP64 sums, then summed) against
+    the same shots one after another: equal up to FP64 summation order."""
+    import paper_2311_05038_amd as fd
+    from paper_2311_05038_amd.autograd import l2_misfit_gradient, rtm_image
+    ps = [fi.surface2d(60, 80, 120, seed=47, src_x=x) for x in (10, 30, 50, 70, 40)]
+    p = ps[0]
+    grid = grid_of(p)
+    vtrue = fi.grf_velocity(p.shape, 48, corr_cells=8.0)
+    v0 = torch.from_numpy(fi.gradient_velocity(p.shape).ravel()).cuda()
+    shots = _shots(ps)
+    m = fd.Model(grid, torch.from_numpy(vtrue.ravel()).cuda())
+    st = m.new_state()
+    obs = torch.stack([m.run_shot(st, s).clone() for s in shots])
+    J1, g1 = l2_misfit_gradient(v0, grid, shots, obs, 16, lanes=1)
+    J3, g3 = l2_misfit_gradient(v0, grid, shots, obs, 16, lanes=3)
+    torch.cuda.synchronize()
+    assert abs(J3 - J1) <= 1e-12 * abs(J1)
+    assert torch.allclose(g3, g1, rtol=1e-12, atol=1e-12 * float(g1.abs().max()))
+    i1 = rtm_image(v0, grid, shots, obs, 16, lanes=1)
+    i3 = rtm_image(v0, grid, shots, obs, 16, lanes=3)
+    torch.cuda.synchronize()
+    assert torch.allclose(i3, i1, rtol=1e-12, atol=1e-12 * float(i1.abs().max()))
+
+
 def test_serving_mix_equals_alone_bitwise():
     import paper_2311_05038_amd as fd
     from paper_2311_05038_amd.serve import Request, Scheduler, TorchDevice
