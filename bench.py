@@ -161,18 +161,18 @@ def adjoint_leg(nt: int = 2000, every: int = 50):
     img = rtm_image(v0t, grid, shots, obs, every)
     torch.cuda.synchronize()
     sec_img = time.perf_counter() - t
-    # the same gradient with the shots one after another on one stream
-    l2_misfit_gradient(v0t, grid, shots, obs, every, lanes=1)
+    # the same gradient with one shot per call (one launch per shot and step)
+    l2_misfit_gradient(v0t, grid, shots, obs, every, group=1)
     torch.cuda.synchronize()
     t = time.perf_counter()
-    l2_misfit_gradient(v0t, grid, shots, obs, every, lanes=1)
+    l2_misfit_gradient(v0t, grid, shots, obs, every, group=1)
     torch.cuda.synchronize()
     sec_1 = time.perf_counter() - t
     out = dict(workload="adjoint2d 1024^2, 8 shots, nt=2000, K=50", seconds_per_gradient=round(sec, 3),
                forward_equiv_mcell_per_s=round(3 * cells / sec / 1e6, 1), misfit=J,
                grad_norm=float(g.norm()), seconds_per_rtm_image=round(sec_img, 3),
-               image_norm=float(img.norm()), shot_lanes=4,
-               seconds_per_gradient_one_lane=round(sec_1, 3))
+               image_norm=float(img.norm()), shots_per_launch=len(shots),
+               seconds_per_gradient_one_shot_per_launch=round(sec_1, 3))
     log(f"[bench] adjoint leg: {out}")
     return out
 

@@ -191,6 +191,34 @@ fd_status fd_rtm_image(const fd_model *model, const fd_shot *shot, const float *
                        const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every, void *work,
                        size_t work_bytes, double *image, void *stream);
 
+/* Several shots on one model at once (the shots of one survey: a
+ * gradient or an image sums over them).  `count` entries in each array;
+ * all shots share nt.  In 2D with FP32 storage every time step of all the
+ * shots is one launch of the batched step kernel (groups of FD_BATCH_MAX),
+ * which keeps the device full on grids too small to fill it alone; otherwise
+ * the shots run one after another.  Per shot, the results are those of the
+ * single-shot call, bit for bit:
+ *   fd_run_shots               = fd_run_shot on each (states[i], shots[i],
+ *                                traces[i], ckpt[i]); traces or ckpt (the
+ *                                arrays or entries) may be NULL.
+ *   fd_adjoint_gradient_shots  = fd_adjoint_gradient on each shot in turn
+ *                                (grad_v += shot 0, then shot 1, ...).
+ *   fd_rtm_image_shots         = fd_rtm_image on each shot in turn.
+ * Every shot needs its own state, checkpoint buffer and work buffer
+ * (sizes as for the single-shot calls); 1 <= count <= 4096. */
+fd_status fd_run_shots(const fd_model *model, fd_state *const *states, const fd_shot *const *shots,
+                       int32_t count, float *const *traces, void *const *ckpt, size_t ckpt_bytes,
+                       int32_t ckpt_every, void *stream);
+fd_status fd_adjoint_gradient_shots(const fd_model *model, const fd_shot *const *shots,
+                                    int32_t count, const float *const *adj,
+                                    const void *const *ckpt, size_t ckpt_bytes, int32_t ckpt_every,
+                                    void *const *work, size_t work_bytes, double *grad_v,
+                                    void *stream);
+fd_status fd_rtm_image_shots(const fd_model *model, const fd_shot *const *shots, int32_t count,
+                             const float *const *data, const void *const *ckpt, size_t ckpt_bytes,
+                             int32_t ckpt_every, void *const *work, size_t work_bytes,
+                             double *image, void *stream);
+
 /* Copies P (which = 0) or Pold (which = 1) of the state, decoded to FP32,
  * into `out` (device, dense [nz][ny][nx]).  After k steps P holds the new
  * field of step k-1 plus the source addition of step k (none after the

@@ -190,6 +190,57 @@ class Model:
                           _stream_handle(stream))
         return image
 
+    # ---- several shots at once (fd_run_shots / fd_*_shots) ----------------
+    def run_shots(self, states: Sequence["State"], shots: Sequence[Shot],
+                  traces: Optional[torch.Tensor] = None,
+                  ckpts: Optional[Sequence[torch.Tensor]] = None, ckpt_every: int = 0,
+                  stream=None) -> torch.Tensor:
+        """fd_run_shots: every shot of `shots` with its own state (and
+        checkpoint buffer); traces [nshots, nt, nrec]."""
+        nt = shots[0].nt
+        nrec = max(shots[0].nrec, 1)
+        if traces is None:
+            traces = torch.empty((len(shots), nt, nrec), dtype=torch.float32, device=self.device)
+        _abi.fd_run_shots(self.handle, [st.handle for st in states], [s._c for s in shots],
+                          [traces[i].data_ptr() if s.nrec > 0 else None for i, s in enumerate(shots)],
+                          [c.data_ptr() for c in ckpts] if ckpts is not None else None,
+                          ckpts[0].numel() if ckpts is not None else 0, ckpt_every,
+                          _stream_handle(stream))
+        for st in states:
+            st.next = nt
+        return traces
+
+    def _backward_shots(self, fn, shots, srcs, ckpts, ckpt_every, out, works, stream):
+        for t in srcs:
+            if t.dtype != torch.float32 or not t.is_contiguous():
+                raise ValueError("adjoint sources must be contiguous FP32")
+        if out.dtype != torch.float64 or out.numel() != self.grid.ncells:
+            raise ValueError("the output must be an FP64 tensor of the grid's size")
+        need = self.sizes_for(shots[0].nt, ckpt_every).adjoint_work
+        if works is None:
+            works = [_alloc(need, self.device) for _ in shots]
+        fn(self.handle, [s._c for s in shots], [t.data_ptr() for t in srcs],
+           [c.data_ptr() for c in ckpts], ckpts[0].numel(), ckpt_every,
+           [w.data_ptr() for w in works], works[0].numel(), out.data_ptr(), _stream_handle(stream))
+        return out
+
+    def adjoint_gradient_shots(self, shots: Sequence[Shot], adj: Sequence[torch.Tensor],
+                               ckpts: Sequence[torch.Tensor], ckpt_every: int,
+                               grad_v: torch.Tensor,
+                               works: Optional[Sequence[torch.Tensor]] = None,
+                               stream=None) -> torch.Tensor:
+        """fd_adjoint_gradient_shots: grad_v += the gradient of every shot."""
+        return self._backward_shots(_abi.fd_adjoint_gradient_shots, shots, adj, ckpts, ckpt_every,
+                                    grad_v, works, stream)
+
+    def rtm_image_shots(self, shots: Sequence[Shot], data: Sequence[torch.Tensor],
+                        ckpts: Sequence[torch.Tensor], ckpt_every: int, image: torch.Tensor,
+                        works: Optional[Sequence[torch.Tensor]] = None,
+                        stream=None) -> torch.Tensor:
+        """fd_rtm_image_shots: image += the image of every shot."""
+        return self._backward_shots(_abi.fd_rtm_image_shots, shots, data, ckpts, ckpt_every,
+                                    image, works, stream)
+
     def __del__(self):
         h = getattr(self, "handle", None)
         if h:

@@ -78,6 +78,9 @@ SIGNATURES = [
      [_P, ctypes.POINTER(fd_shot), _P, _P, _SZ, _I32, _P, _SZ, _P, _P]),
     ("fd_rtm_image", ctypes.c_int,
      [_P, ctypes.POINTER(fd_shot), _P, _P, _SZ, _I32, _P, _SZ, _P, _P]),
+    ("fd_run_shots", ctypes.c_int, [_P, _P, _P, _I32, _P, _P, _SZ, _I32, _P]),
+    ("fd_adjoint_gradient_shots", ctypes.c_int, [_P, _P, _I32, _P, _P, _SZ, _I32, _P, _SZ, _P, _P]),
+    ("fd_rtm_image_shots", ctypes.c_int, [_P, _P, _I32, _P, _P, _SZ, _I32, _P, _SZ, _P, _P]),
     ("fd_get_wavefield", ctypes.c_int, [_P, _I32, _P, _P]),
     ("fd_set_wavefield", ctypes.c_int, [_P, _I32, _P, _P]),
     ("fd_step_batch", ctypes.c_int, [ctypes.POINTER(fd_batch_item), _I32, _I32, _P]),
@@ -179,6 +182,42 @@ def fd_rtm_image(model: int, shot: fd_shot, data_ptr: int, ckpt_ptr: int, ckpt_b
                  stream: int) -> None:
     check(lib().fd_rtm_image(model, ctypes.byref(shot), data_ptr, ckpt_ptr, ckpt_bytes,
                              ckpt_every, work_ptr, work_bytes, image_ptr, stream))
+
+
+def _ptrs(values):
+    """A C array of pointers (None -> NULL) and the array object to keep alive."""
+    arr = (ctypes.c_void_p * len(values))(*[v if v else None for v in values])
+    return ctypes.cast(arr, ctypes.c_void_p), arr
+
+
+def fd_run_shots(model: int, states, shots, traces_ptrs, ckpt_ptrs, ckpt_bytes: int,
+                 ckpt_every: int, stream: int) -> None:
+    st, a1 = _ptrs(states)
+    sh, a2 = _ptrs([ctypes.addressof(s) for s in shots])
+    tr, a3 = _ptrs(traces_ptrs) if traces_ptrs is not None else (None, None)
+    ck, a4 = _ptrs(ckpt_ptrs) if ckpt_ptrs is not None else (None, None)
+    check(lib().fd_run_shots(model, st, sh, len(shots), tr, ck, ckpt_bytes, ckpt_every, stream))
+
+
+def fd_adjoint_gradient_shots(model: int, shots, adj_ptrs, ckpt_ptrs, ckpt_bytes: int,
+                              ckpt_every: int, work_ptrs, work_bytes: int, grad_v_ptr: int,
+                              stream: int) -> None:
+    sh, a1 = _ptrs([ctypes.addressof(s) for s in shots])
+    ad, a2 = _ptrs(adj_ptrs)
+    ck, a3 = _ptrs(ckpt_ptrs)
+    wk, a4 = _ptrs(work_ptrs)
+    check(lib().fd_adjoint_gradient_shots(model, sh, len(shots), ad, ck, ckpt_bytes, ckpt_every,
+                                          wk, work_bytes, grad_v_ptr, stream))
+
+
+def fd_rtm_image_shots(model: int, shots, data_ptrs, ckpt_ptrs, ckpt_bytes: int, ckpt_every: int,
+                       work_ptrs, work_bytes: int, image_ptr: int, stream: int) -> None:
+    sh, a1 = _ptrs([ctypes.addressof(s) for s in shots])
+    dt, a2 = _ptrs(data_ptrs)
+    ck, a3 = _ptrs(ckpt_ptrs)
+    wk, a4 = _ptrs(work_ptrs)
+    check(lib().fd_rtm_image_shots(model, sh, len(shots), dt, ck, ckpt_bytes, ckpt_every, wk,
+                                   work_bytes, image_ptr, stream))
 
 
 def fd_get_wavefield(state: int, which: int, out_ptr: int, stream: int) -> None:

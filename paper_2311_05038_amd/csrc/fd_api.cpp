@@ -424,75 +424,195 @@ fd_status fd_run_shot(const fd_model *model, fd_state *state, const fd_shot *sho
     return ok();
 }
 
+fd_status fd_run_shots(const fd_model *model, fd_state *const *states, const fd_shot *const *shots,
+                       int32_t count, float *const *traces, void *const *ckpt, size_t ckpt_bytes,
+                       int32_t ckpt_every, void *stream)
+{
+    if (!model) return fail(FD_ERR_INVALID_ARG, "NULL model");
+    if (count < 1 || count > 4096) return fail(FD_ERR_INVALID_ARG, "count must be in [1, 4096]");
+    if (!states || !shots) return fail(FD_ERR_INVALID_ARG, "NULL states or shots array");
+    const Layout &L = model->L;
+    for (int32_t i = 0; i < count; ++i) {
+        if (!states[i] || states[i]->m != model) return fail(FD_ERR_INVALID_ARG, "shot %d: state missing or of another model", i);
+        fd_status st = check_shot(model, shots[i]);
+        if (st != FD_OK) return st;
+        if (shots[i]->nt != shots[0]->nt) return fail(FD_ERR_INVALID_ARG, "shot %d: all shots must share nt", i);
+        for (int32_t j = 0; j < i; ++j)
+            if (states[j] == states[i]) return fail(FD_ERR_INVALID_ARG, "shot %d repeats a state", i);
+        if (ckpt && ckpt[i]) {
+            if (ckpt_every < 1) return fail(FD_ERR_INVALID_ARG, "ckpt_every must be >= 1");
+            const size_t need = (size_t)n_ckpt(shots[i]->nt, ckpt_every) * ckpt_slot_bytes(L);
+            if (ckpt_bytes < need)
+                return fail(FD_ERR_INVALID_ARG, "checkpoint buffer too small (%zu < %zu bytes)", ckpt_bytes, need);
+            if ((uintptr_t)ckpt[i] % kAlign) return fail(FD_ERR_INVALID_ARG, "checkpoint buffer must be 256-byte aligned");
+        }
+    }
+    hipStream_t s = (hipStream_t)stream;
+    const bool batched = L.ndim == 2 && L.storage == FD_F32 && count > 1;
+    if (!batched) {
+        for (int32_t i = 0; i < count; ++i) {
+            fd_status st = fd_run_shot(model, states[i], shots[i], traces ? traces[i] : nullptr,
+                                       ckpt ? ckpt[i] : nullptr, ckpt_bytes, ckpt_every, stream);
+            if (st != FD_OK) return st;
+        }
+        return ok();
+    }
+    for (int32_t i = 0; i < count; ++i) {
+        fd_status st = do_begin(model, states[i], shots[i], s);
+        if (st != FD_OK) return st;
+    }
+    const int64_t nt = shots[0]->nt;
+    for (int64_t n = 0; n < nt; ++n) {
+        for (int32_t i0 = 0; i0 < count; i0 += FD_BATCH_MAX) {
+            fdk::Batch2D b;
+            b.count = 0;
+            for (int32_t i = i0; i < std::min<int32_t>(count, i0 + FD_BATCH_MAX); ++i) {
+                fd_state *st = states[i];
+                if (ckpt && ckpt[i] && n % ckpt_every == 0) {
+                    char *slot = (char *)ckpt[i] + (size_t)(n / ckpt_every) * ckpt_slot_bytes(L);
+                    hipError_t e = hipMemcpyAsync(slot, st->buf[n & 1], L.field, hipMemcpyDeviceToDevice, s);
+                    if (e == hipSuccess)
+                        e = hipMemcpyAsync(slot + L.field, st->buf[(n + 1) & 1], L.field, hipMemcpyDeviceToDevice, s);
+                    if (e != hipSuccess) return hip_fail(e, "checkpoint copy");
+                }
+                StepArgs a = base_args(model, shots[i]);
+                a.cur = st->buf[n & 1];
+                a.prev = st->buf[(n + 1) & 1];
+                a.n = n;
+                const int64_t nrec = nrec_of(shots[i]);
+                a.trace_row = (traces && traces[i] && nrec > 0) ? traces[i] + (size_t)n * (size_t)nrec : nullptr;
+                a.meta = st->meta;
+                b.it[b.count++] = a;
+            }
+            hipError_t e = fdk::launch_step_batch2d(b, fdk::kFwd, s);
+            if (e != hipSuccess) return hip_fail(e, "batched step launch");
+        }
+        for (int32_t i = 0; i < count; ++i) states[i]->next = n + 1;
+    }
+    return ok();
+}
+
 }  // extern "C"
 
 namespace {
 
-// Checkpointed backward pass shared by the gradient and the image: each
-// segment is recomputed storing the history field of every step (L w^n for
-// the gradient, w^n for the image), then the z-form adjoint field is
-// stepped back through the segment accumulating sum_k z^k * hist^{k-1} in
-// FP64.  On success *acc points at that sum (padded, inside `work`).
-fd_status backward_pass(const fd_model *model, const fd_shot *shot, const float *adj,
-                        const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every, void *work,
-                        size_t work_bytes, int hist_mode, hipStream_t s, double **acc)
+// Checkpointed backward pass shared by the gradient and the image, for
+// `count` shots on one model: each segment is recomputed storing the
+// history field of every step (L w^n for the gradient, w^n for the image),
+// then the z-form adjoint field is stepped back through the segment
+// accumulating sum_k z^k * hist^{k-1} in FP64, one sum per shot (acc[i],
+// padded, inside work[i]).  In 2D FP32 every step of all shots is one
+// launch of the batched kernel (groups of FD_BATCH_MAX shots); otherwise
+// the shots' steps are launched one by one.  Per shot and cell the
+// arithmetic is the same either way.
+struct ShotIO {
+    const fd_shot *shot;
+    const float *adj;
+    const void *ckpt;
+    void *work;
+};
+
+fd_status backward_pass(const fd_model *model, const ShotIO *io, int32_t count, size_t ckpt_bytes,
+                        int32_t ckpt_every, size_t work_bytes, int hist_mode, hipStream_t s,
+                        double **acc)
 {
-    fd_status st = check_shot(model, shot);
-    if (st != FD_OK) return st;
     const Layout &L = model->L;
     if (L.storage != FD_F32) return fail(FD_ERR_UNSUPPORTED, "the adjoint needs FP32 storage");
-    if (!adj || !ckpt || !work) return fail(FD_ERR_INVALID_ARG, "NULL adj, ckpt or work");
     if (ckpt_every < 1) return fail(FD_ERR_INVALID_ARG, "ckpt_every must be >= 1");
-    const int64_t nt = shot->nt;
+    if (count < 1) return fail(FD_ERR_INVALID_ARG, "count must be >= 1");
+    for (int32_t i = 0; i < count; ++i) {
+        fd_status st = check_shot(model, io[i].shot);
+        if (st != FD_OK) return st;
+        if (!io[i].adj || !io[i].ckpt || !io[i].work) return fail(FD_ERR_INVALID_ARG, "shot %d: NULL adj, ckpt or work", i);
+        if (io[i].shot->nt != io[0].shot->nt) return fail(FD_ERR_INVALID_ARG, "shot %d: all shots must share nt", i);
+        if ((uintptr_t)io[i].work % kAlign) return fail(FD_ERR_INVALID_ARG, "work buffer must be 256-byte aligned");
+        for (int32_t j = 0; j < i; ++j)
+            if (io[j].work == io[i].work) return fail(FD_ERR_INVALID_ARG, "shot %d repeats a work buffer", i);
+    }
+    const int64_t nt = io[0].shot->nt;
     const int64_t nseg = n_ckpt(nt, ckpt_every);
     if (ckpt_bytes < (size_t)nseg * ckpt_slot_bytes(L))
         return fail(FD_ERR_INVALID_ARG, "checkpoint buffer too small");
     if (work_bytes < adjoint_work_bytes(L, ckpt_every))
         return fail(FD_ERR_INVALID_ARG, "adjoint work buffer too small (%zu < %zu bytes)", work_bytes,
                     adjoint_work_bytes(L, ckpt_every));
-    if ((uintptr_t)work % kAlign) return fail(FD_ERR_INVALID_ARG, "work buffer must be 256-byte aligned");
-    char *w = (char *)work;
-    void *fw[2] = {w, w + L.f32field};
-    float *hist = (float *)(w + 2 * L.f32field);
-    char *zb = w + 2 * L.f32field + (size_t)ckpt_every * L.f32field;
-    void *zf[2] = {zb, zb + L.f32field};
-    double *g = (double *)(zb + 2 * L.f32field);
-    const int64_t nrec = nrec_of(shot);
+    // work layout: recompute state (2), history (K), adjoint state (2), FP64 sum
+    auto fw = [&](int32_t i, int64_t n) -> void * { return (char *)io[i].work + (size_t)(n & 1) * L.f32field; };
+    auto hist = [&](int32_t i, int64_t slot) -> float * {
+        return (float *)((char *)io[i].work + (2 + (size_t)slot) * L.f32field);
+    };
+    auto zf = [&](int32_t i, int64_t k) -> void * {
+        return (char *)io[i].work + (2 + (size_t)ckpt_every + (size_t)(k & 1)) * L.f32field;
+    };
+    auto gsum = [&](int32_t i) -> double * {
+        return (double *)((char *)io[i].work + (4 + (size_t)ckpt_every) * L.f32field);
+    };
+    const bool batched = L.ndim == 2 && count > 1;
+    // one step of every shot: batched launches in 2D, one launch per shot otherwise
+    auto launch_all = [&](auto make_args, int mode) -> hipError_t {
+        if (!batched) {
+            for (int32_t i = 0; i < count; ++i) {
+                hipError_t e = fdk::launch_step(make_args(i), L.ndim, L.storage, mode, s);
+                if (e != hipSuccess) return e;
+            }
+            return hipSuccess;
+        }
+        for (int32_t i0 = 0; i0 < count; i0 += FD_BATCH_MAX) {
+            fdk::Batch2D b;
+            b.count = 0;
+            for (int32_t i = i0; i < std::min<int32_t>(count, i0 + FD_BATCH_MAX); ++i) b.it[b.count++] = make_args(i);
+            hipError_t e = fdk::launch_step_batch2d(b, mode, s);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    };
 
-    hipError_t e = fdk::launch_fill_u32(zf[0], (2 * L.f32field + align_up(L.npad * 8)) / 4, 0u, s);
-    if (e != hipSuccess) return hip_fail(e, "adjoint clear");
+    for (int32_t i = 0; i < count; ++i) {
+        hipError_t e = fdk::launch_fill_u32(zf(i, 0), (2 * L.f32field + align_up(L.npad * 8)) / 4, 0u, s);
+        if (e != hipSuccess) return hip_fail(e, "adjoint clear");
+    }
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t n0 = seg * ckpt_every;
         const int64_t n1 = std::min<int64_t>(nt, n0 + ckpt_every);
-        const char *slot = (const char *)ckpt + (size_t)seg * ckpt_slot_bytes(L);
-        e = hipMemcpyAsync(fw[n0 & 1], slot, L.field, hipMemcpyDeviceToDevice, s);
-        if (e == hipSuccess)
-            e = hipMemcpyAsync(fw[(n0 + 1) & 1], slot + L.field, L.field, hipMemcpyDeviceToDevice, s);
-        if (e != hipSuccess) return hip_fail(e, "checkpoint restore");
+        for (int32_t i = 0; i < count; ++i) {
+            const char *slot = (const char *)io[i].ckpt + (size_t)seg * ckpt_slot_bytes(L);
+            hipError_t e = hipMemcpyAsync(fw(i, n0), slot, L.field, hipMemcpyDeviceToDevice, s);
+            if (e == hipSuccess) e = hipMemcpyAsync(fw(i, n0 + 1), slot + L.field, L.field, hipMemcpyDeviceToDevice, s);
+            if (e != hipSuccess) return hip_fail(e, "checkpoint restore");
+        }
         for (int64_t n = n0; n < n1; ++n) {
-            StepArgs a = base_args(model, shot);
-            a.cur = fw[n & 1];
-            a.prev = fw[(n + 1) & 1];
-            a.n = n;
-            a.trace_row = nullptr;
-            a.lap = (float *)((char *)hist + (size_t)(n - n0) * L.f32field);
-            e = fdk::launch_step(a, L.ndim, L.storage, hist_mode, s);
+            hipError_t e = launch_all(
+                [&](int32_t i) {
+                    StepArgs a = base_args(model, io[i].shot);
+                    a.cur = fw(i, n);
+                    a.prev = fw(i, n + 1);
+                    a.n = n;
+                    a.trace_row = nullptr;
+                    a.lap = hist(i, n - n0);
+                    return a;
+                },
+                hist_mode);
             if (e != hipSuccess) return hip_fail(e, "recompute step");
         }
         for (int64_t k = n1; k >= n0 + 1; --k) {
-            StepArgs a = base_args(model, shot);
-            a.cur = zf[(k + 1) & 1];
-            a.prev = zf[k & 1];
-            a.n = k;
-            a.nt = 0;  // no source in the adjoint recursion
-            a.lap = (float *)((char *)hist + (size_t)(k - 1 - n0) * L.f32field);
-            a.resid_row = nrec > 0 ? adj + (size_t)(k - 1) * (size_t)nrec : nullptr;
-            a.g = g;
-            e = fdk::launch_step(a, L.ndim, L.storage, fdk::kAdj, s);
+            hipError_t e = launch_all(
+                [&](int32_t i) {
+                    StepArgs a = base_args(model, io[i].shot);
+                    const int64_t nrec = nrec_of(io[i].shot);
+                    a.cur = zf(i, k + 1);
+                    a.prev = zf(i, k);
+                    a.n = k;
+                    a.nt = 0;  // no source in the adjoint recursion
+                    a.lap = hist(i, k - 1 - n0);
+                    a.resid_row = nrec > 0 ? io[i].adj + (size_t)(k - 1) * (size_t)nrec : nullptr;
+                    a.g = gsum(i);
+                    return a;
+                },
+                fdk::kAdj);
             if (e != hipSuccess) return hip_fail(e, "adjoint step");
         }
     }
-    *acc = g;
+    for (int32_t i = 0; i < count; ++i) acc[i] = gsum(i);
     return FD_OK;
 }
 
@@ -504,35 +624,66 @@ fd_status fd_adjoint_gradient(const fd_model *model, const fd_shot *shot, const 
                               const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every, void *work,
                               size_t work_bytes, double *grad_v, void *stream)
 {
-    if (!model) return fail(FD_ERR_INVALID_ARG, "NULL model");
-    if (!grad_v) return fail(FD_ERR_INVALID_ARG, "NULL grad_v");
-    hipStream_t s = (hipStream_t)stream;
-    double *g = nullptr;
-    fd_status st = backward_pass(model, shot, adj, ckpt, ckpt_bytes, ckpt_every, work, work_bytes,
-                                 fdk::kFwdLap, s, &g);
-    if (st != FD_OK) return st;
-    const Layout &L = model->L;
-    hipError_t e = fdk::launch_grad_finish(g, model->c, grad_v, L.nz * L.ny, (int32_t)L.nx, L.px,
-                                           2.0 * model->grid.dt / model->grid.dh, s);
-    if (e != hipSuccess) return hip_fail(e, "gradient finish");
-    return ok();
+    return fd_adjoint_gradient_shots(model, &shot, 1, &adj, &ckpt, ckpt_bytes, ckpt_every, &work,
+                                     work_bytes, grad_v, stream);
 }
 
 fd_status fd_rtm_image(const fd_model *model, const fd_shot *shot, const float *data,
                        const void *ckpt, size_t ckpt_bytes, int32_t ckpt_every, void *work,
                        size_t work_bytes, double *image, void *stream)
 {
+    return fd_rtm_image_shots(model, &shot, 1, &data, &ckpt, ckpt_bytes, ckpt_every, &work,
+                              work_bytes, image, stream);
+}
+
+namespace {
+
+fd_status backward_shots(const fd_model *model, const fd_shot *const *shots, int32_t count,
+                         const float *const *adj, const void *const *ckpt, size_t ckpt_bytes,
+                         int32_t ckpt_every, void *const *work, size_t work_bytes, double *out,
+                         bool image, void *stream)
+{
     if (!model) return fail(FD_ERR_INVALID_ARG, "NULL model");
-    if (!image) return fail(FD_ERR_INVALID_ARG, "NULL image");
+    if (!out) return fail(FD_ERR_INVALID_ARG, image ? "NULL image" : "NULL grad_v");
+    if (count < 1 || count > 4096) return fail(FD_ERR_INVALID_ARG, "count must be in [1, 4096]");
+    if (!shots || !adj || !ckpt || !work) return fail(FD_ERR_INVALID_ARG, "NULL shots, adj, ckpt or work array");
+    std::vector<ShotIO> io((size_t)count);
+    for (int32_t i = 0; i < count; ++i) io[i] = ShotIO{shots[i], adj[i], ckpt[i], work[i]};
     hipStream_t s = (hipStream_t)stream;
-    double *g = nullptr;
-    fd_status st = backward_pass(model, shot, data, ckpt, ckpt_bytes, ckpt_every, work, work_bytes,
-                                 fdk::kFwdKeep, s, &g);
+    std::vector<double *> acc((size_t)count, nullptr);
+    fd_status st = backward_pass(model, io.data(), count, ckpt_bytes, ckpt_every, work_bytes,
+                                 image ? fdk::kFwdKeep : fdk::kFwdLap, s, acc.data());
     if (st != FD_OK) return st;
     const Layout &L = model->L;
-    hipError_t e = fdk::launch_image_finish(g, image, L.nz * L.ny, (int32_t)L.nx, L.px, s);
-    if (e != hipSuccess) return hip_fail(e, "image finish");
+    // shot after shot, so the FP64 sum has the order of one call per shot
+    for (int32_t i = 0; i < count; ++i) {
+        hipError_t e = image ? fdk::launch_image_finish(acc[i], out, L.nz * L.ny, (int32_t)L.nx, L.px, s)
+                             : fdk::launch_grad_finish(acc[i], model->c, out, L.nz * L.ny, (int32_t)L.nx,
+                                                       L.px, 2.0 * model->grid.dt / model->grid.dh, s);
+        if (e != hipSuccess) return hip_fail(e, image ? "image finish" : "gradient finish");
+    }
     return ok();
+}
+
+}  // namespace
+
+fd_status fd_adjoint_gradient_shots(const fd_model *model, const fd_shot *const *shots,
+                                    int32_t count, const float *const *adj,
+                                    const void *const *ckpt, size_t ckpt_bytes, int32_t ckpt_every,
+                                    void *const *work, size_t work_bytes, double *grad_v,
+                                    void *stream)
+{
+    return backward_shots(model, shots, count, adj, ckpt, ckpt_bytes, ckpt_every, work, work_bytes,
+                          grad_v, false, stream);
+}
+
+fd_status fd_rtm_image_shots(const fd_model *model, const fd_shot *const *shots, int32_t count,
+                             const float *const *data, const void *const *ckpt, size_t ckpt_bytes,
+                             int32_t ckpt_every, void *const *work, size_t work_bytes,
+                             double *image, void *stream)
+{
+    return backward_shots(model, shots, count, data, ckpt, ckpt_bytes, ckpt_every, work, work_bytes,
+                          image, true, stream);
 }
 
 fd_status fd_get_wavefield(const fd_state *state, int32_t which, float *out, void *stream)
@@ -637,7 +788,7 @@ fd_status fd_step_batch(fd_batch_item *items, int32_t count, int32_t nsteps, voi
             ++b.count;
         }
         if (b.count == 0) break;
-        hipError_t e = fdk::launch_step_batch2d(b, s);
+        hipError_t e = fdk::launch_step_batch2d(b, fdk::kFwd, s);
         if (e != hipSuccess) return hip_fail(e, "batched step launch");
         for (int32_t k = 0; k < b.count; ++k) {
             fd_batch_item &it = items[which[k]];

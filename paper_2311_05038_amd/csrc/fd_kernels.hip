@@ -329,9 +329,9 @@ __global__ __launch_bounds__(64) void k_step2d(StepArgs a)
         block_max_to<64>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax * h.sn, nullptr);
 }
 
-// Batched 2D FP32 forward step: block b belongs to the item whose tile range
-// holds b; every item keeps its own grid, fields and step index.
-template <int VX>
+// Batched 2D FP32 step (any mode): block b belongs to the item whose tile
+// range holds b; every item keeps its own grid, fields and step index.
+template <int VX, int MODE>
 __global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
 {
     __shared__ float row[2][64 * VX + 8];
@@ -341,10 +341,12 @@ __global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
     const StepArgs &a = b.it[i];
     const int lt = t - b.begin[i];
     const int tx = lt % a.tiles_x, tz = lt / a.tiles_x;
-    const float inj = (a.n + 1 < a.nt) ? a.amp * a.wavelet[a.n + 1] : 0.0f;
+    float inj = 0.0f;
+    if constexpr (MODE != kAdj)
+        if (a.n + 1 < a.nt) inj = a.amp * a.wavelet[a.n + 1];
     const HalfCtx h{1.0f, 1.0f, 1.0f, 1.0f};
     float bmax = 0.0f;
-    step2d_tile<kF32, VX, kFwd>(a, tx, tz, row, h, inj, bmax);
+    step2d_tile<kF32, VX, MODE>(a, tx, tz, row, h, inj, bmax);
 }
 
 // --------------------------------------------------------------------------
@@ -1061,7 +1063,7 @@ hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t 
     return hipGetLastError();
 }
 
-hipError_t launch_step_batch2d(Batch2D &b, hipStream_t s)
+hipError_t launch_step_batch2d(Batch2D &b, int mode, hipStream_t s)
 {
     int total = 0;
     for (int i = 0; i < b.count; ++i) {
@@ -1071,7 +1073,12 @@ hipError_t launch_step_batch2d(Batch2D &b, hipStream_t s)
     }
     b.begin[b.count] = total;
     if (total == 0) return hipSuccess;
-    hipLaunchKernelGGL((k_step2d_batch<kBatchVX>), dim3(total), dim3(64), 0, s, b);
+    switch (mode) {
+    case kFwd: hipLaunchKernelGGL((k_step2d_batch<kBatchVX, kFwd>), dim3(total), dim3(64), 0, s, b); break;
+    case kFwdLap: hipLaunchKernelGGL((k_step2d_batch<kBatchVX, kFwdLap>), dim3(total), dim3(64), 0, s, b); break;
+    case kFwdKeep: hipLaunchKernelGGL((k_step2d_batch<kBatchVX, kFwdKeep>), dim3(total), dim3(64), 0, s, b); break;
+    default: hipLaunchKernelGGL((k_step2d_batch<kBatchVX, kAdj>), dim3(total), dim3(64), 0, s, b); break;
+    }
     return hipGetLastError();
 }
 

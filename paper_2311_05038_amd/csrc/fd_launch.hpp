@@ -23,7 +23,7 @@ static_assert(sizeof(Batch2D) <= 4096, "batched step arguments must fit the kern
 void plan_tiles(StepArgs &a, int ndim, int storage, bool batched);
 
 hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t s);
-hipError_t launch_step_batch2d(Batch2D &b, hipStream_t s);
+hipError_t launch_step_batch2d(Batch2D &b, int mode, hipStream_t s);
 // The step as separate routine kernels (derivative fields dzz, dxx and, in
 // 3D, dyy materialised in HBM); FP32 fields only.
 hipError_t launch_routines(const StepArgs &a, int ndim, float *dzz, float *dxx, float *dyy,
