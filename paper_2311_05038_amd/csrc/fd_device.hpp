@@ -121,43 +121,27 @@ template <> struct Raw<8> { typedef unsigned int type __attribute__((ext_vector_
 template <> struct Raw<16> { typedef unsigned int type __attribute__((ext_vector_type(4))); };
 template <> struct Raw<32> { typedef unsigned int type __attribute__((ext_vector_type(8))); };
 
-#ifndef FD_NT
-#define FD_NT 1
-#endif
-
 // Streaming (read-once / write-once) accesses: Pold, c and Pnew are touched
 // once per step, so they are marked non-temporal to leave the L2 to the
 // current field, whose planes neighbouring tiles re-read as halos.
 template <typename T, int VX>
 __device__ __forceinline__ Pack<T, VX> ldp_stream(const T *p)
 {
-#if FD_NT
     using R = typename Raw<sizeof(T) * VX>::type;
     const R r = __builtin_nontemporal_load(reinterpret_cast<const R *>(p));
     Pack<T, VX> o;
     __builtin_memcpy(&o, &r, sizeof(o));
     return o;
-#else
-    return ldp<T, VX>(p);
-#endif
 }
 
 template <typename T, int VX>
 __device__ __forceinline__ void stp_stream(T *p, const Pack<T, VX> &x)
 {
-#if FD_NT
     using R = typename Raw<sizeof(T) * VX>::type;
     R r;
     __builtin_memcpy(&r, &x, sizeof(r));
     __builtin_nontemporal_store(r, reinterpret_cast<R *>(p));
-#else
-    stp<T, VX>(p, x);
-#endif
 }
-
-#ifndef FD_F16_BITS
-#define FD_F16_BITS 1
-#endif
 
 template <int ST>
 __device__ __forceinline__ float decode(typename Stor<ST>::T q, float scale)
@@ -181,12 +165,13 @@ __device__ __forceinline__ float f16_bits_scaled(uint16_t q)
 }
 
 // Decode used inside the step kernels, before the power-of-two field scale:
-// FP32 and bfloat16 exactly, binary16 either exactly (hardware conversion)
-// or times 2^-112 (bit move; the 2^112 goes into the update's coefficients).
+// FP32 and bfloat16 exactly, binary16 times 2^-112 by the bit move (the
+// 2^112 goes into the update's coefficients; the hardware conversion
+// measured slower in the step kernel).
 template <int ST>
 __device__ __forceinline__ float decode_raw(typename Stor<ST>::T q)
 {
-    if constexpr (ST == kF16 && FD_F16_BITS)
+    if constexpr (ST == kF16)
         return f16_bits_scaled(q);
     else
         return decode<ST>(q, 1.0f);
@@ -289,7 +274,7 @@ __device__ __forceinline__ HalfCtx half_prologue(const StepArgs &a, float inj, b
         const int en = storage_exponent(m);
         // ec - en and ep - en stay within a few units (the magnitude changes
         // by a bounded factor per step); the clamp only keeps 2^k finite.
-        const int bias = (ST == kF16 && FD_F16_BITS) ? 112 : 0;
+        const int bias = ST == kF16 ? 112 : 0;
         h.sc = pow2i(min(ec - en + bias, 127));
         h.sp = pow2i(min(ep - en + bias, 127));
         h.sn = pow2i(en);
@@ -349,10 +334,6 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks)
     return bid;
 }
 
-#ifndef FD_XCD_ROUNDS
-#define FD_XCD_ROUNDS 1
-#endif
-
 // 3D variant.  Blocks run in rounds of `resident` (the blocks the device
 // holds at once; later blocks start, in index order, as earlier ones end).
 // Within each round, XCD k gets the k-th eighth of the round's tiles
@@ -361,7 +342,7 @@ __device__ __forceinline__ int xcd_tile(int bid, int nblocks)
 // chunk length.  A ragged tail (fewer than 8 blocks) keeps its index.
 __device__ __forceinline__ int xcd_tile3d(int bid, int nblocks, int resident)
 {
-    if (!FD_XCD_ROUNDS || resident < 8) return xcd_tile(bid, nblocks);
+    if (resident < 8) return xcd_tile(bid, nblocks);
     const int base = bid / resident * resident;
     const int m8 = min(resident, nblocks - base) & ~7;
     const int w = bid - base;

@@ -18,38 +18,21 @@
 #include "fd_device.hpp"
 #include "fd_launch.hpp"
 
-// 1: unroll the 3D plane loop 9 times so the z register queue rotates by
-// renaming instead of moves (larger code); 0: rolled loop.
-#ifndef FD_UNROLL9
-#define FD_UNROLL9 0
-#endif
-#ifndef FD_OFF32_F32
-#define FD_OFF32_F32 0
-#endif
-// Memory-op ordering of the step loops for FP32 fields (16-bit fields always
-// use all three): store each row/plane one step late, prefetch
-// unconditionally, and carry the z sponge factor with the prefetch.  With
-// them the 16-bit steps overlap the next plane's loads with the compute
-// (768x768x512 BF16 649 -> 566 us); the FP32 steps measured slower with
-// them (512^3 366 -> 387 us), so they are off there.
-#ifndef FD_DEFER32
-#define FD_DEFER32 0
-#endif
-#ifndef FD_UNCOND32
-#define FD_UNCOND32 0
-#endif
-#ifndef FD_GZPF32
-#define FD_GZPF32 0
-#endif
-// 1: 16-bit 3D steps use the reordered (fewer-instruction) FP32 arithmetic.
-#ifndef FD_H16_ARITH
-#define FD_H16_ARITH 1
-#endif
-// 1: tiles wholly inside the grid take a path without per-lane load tests.
-#ifndef FD_FULL_TILES
-#define FD_FULL_TILES 1
-#endif
-
+// The 16-bit steps order their memory operations so that the next plane's
+// loads overlap the compute: the z sponge factor travels with the
+// prefetched data, the prefetch is unconditional (planes past the chunk are
+// in bounds or read as zero), and each new plane is stored one plane late,
+// right before the next prefetch.  Vector loads and stores share one
+// completion counter, and the compiler waits for a load by waiting until
+// every older memory operation has completed once both kinds are
+// outstanding: a load issued after the prefetch and used at once, a
+// skipped prefetch (the previous registers are then copied, which waits),
+// or a store issued right after the compute would each make a plane wait
+// for its own prefetch.  Measured at 768x768x512: BF16 649 -> 566 us.  The
+// FP32 steps keep the plain order (stores right after the compute, the
+// sponge factor loaded after the barrier), which measured faster for them
+// (512^3 366 against 387 us): their loop is bandwidth-bound with more bytes
+// in flight per wave already.
 namespace fdk {
 
 // --------------------------------------------------------------------------
@@ -250,8 +233,7 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
     T hv = ld_halo(zb);
     // the row's sponge factor travels with the prefetch: a load issued after
     // it and waited for in the same row would also wait for the prefetch
-    constexpr bool DEFER = ST != kF32 || FD_DEFER32, UNCOND = ST != kF32 || FD_UNCOND32;
-    constexpr bool GZPF = ST != kF32 || FD_GZPF32;
+    constexpr bool LATE = ST != kF32;   // the 16-bit memory-op order (see top)
     float gn = a.gz[zb];
     Outgoing<T, VX> out;
     out.ok = false;
@@ -268,26 +250,23 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
         const float gzp = gn;
         // the previous row's stores go out after the wait for this row's
         // data and just before the next prefetch
-        if constexpr (DEFER) {
+        if constexpr (LATE) {
             __builtin_amdgcn_sched_barrier(0);
             flush<T, VX, MODE, false>(out);
         }
-        // unconditional (rows past the chunk are in bounds or read as zero):
-        // a skipped prefetch would make the compiler copy the previous
-        // registers, and the copy waits for every outstanding memory access
-        if (UNCOND || z + 1 < ze) {
+        if (LATE || z + 1 < ze) {
             la = ld_cur(z + 5);
             pv = ld_prev(z + 1);
             cv = ld_c(z + 1);
             hv = ld_halo(z + 1);
-            if constexpr (GZPF) gn = z + 1 < nz ? a.gz[z + 1] : 0.0f;
+            if constexpr (LATE) gn = z + 1 < nz ? a.gz[z + 1] : 0.0f;
         }
         float *rw = row[z & 1];
 #pragma unroll
         for (int v = 0; v < VX; ++v) rw[4 + lane * VX + v] = q[4][v];
         if (hlane) rw[hslot] = hc;
         __syncthreads();
-        const float gzz = GZPF ? gzp : a.gz[z];
+        const float gzz = LATE ? gzp : a.gz[z];
         float nw[VX], lp[VX], G[VX];
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
@@ -303,7 +282,7 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
         }
         finish_cells<ST, VX, MODE, false, false>(a, h, z, 0, x0, lane_in, (size_t)z * px, (uint32_t)x0, nw,
                                                  lp, cc, G, inj, bmax, out);
-        if constexpr (!DEFER) flush<T, VX, MODE, false>(out);
+        if constexpr (!LATE) flush<T, VX, MODE, false>(out);
 #pragma unroll
         for (int k = 0; k < 8; ++k)
 #pragma unroll
@@ -352,17 +331,11 @@ __global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
 // --------------------------------------------------------------------------
 // 3D
 // --------------------------------------------------------------------------
-#ifdef FD_MINB16
-#define FD_3D_BOUNDS __launch_bounds__(64 * NW, ST == kF32 ? 1 : FD_MINB16)
-#else
-#define FD_3D_BOUNDS __launch_bounds__(64 * NW)
-#endif
-template <int ST, int VX, int RY, int NW, int MODE, int PFD>
-__global__ FD_3D_BOUNDS void k_step3d(StepArgs a)
+template <int ST, int VX, int RY, int NW, int MODE>
+__global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
 {
     using T = typename Stor<ST>::T;
     static_assert(NW == 2 || NW == 4 || NW == 8, "waves per block");
-    static_assert(PFD == 1 || PFD == 2, "planes prefetched");
     constexpr int TX = 64 * VX, TY = NW * RY, LW = TX + 8, LH = TY + 8, HH = 8 / NW;
     __shared__ float pl[2][LH * LW];
     __shared__ float red[NW];
@@ -433,9 +406,8 @@ __global__ FD_3D_BOUNDS void k_step3d(StepArgs a)
         // cells): each access is a wave-uniform plane pointer plus a lane
         // offset, which keeps the address arithmetic scalar.  (FP32 fields,
         // bandwidth-bound, measured faster with plain 64-bit addresses.)
-        constexpr bool OFF32 = ST != kF32 || FD_OFF32_F32;
-        constexpr bool DEFER = ST != kF32 || FD_DEFER32, UNCOND = ST != kF32 || FD_UNCOND32;
-        constexpr bool GZPF = ST != kF32 || FD_GZPF32;
+        constexpr bool OFF32 = ST != kF32;
+        constexpr bool LATE = ST != kF32;   // the 16-bit memory-op order (see top)
         auto addr = [&](auto *base, int z, uint32_t e, int y, int x) {
             if constexpr (OFF32)
                 return at(base + (size_t)z * pp, e);
@@ -491,14 +463,11 @@ __global__ FD_3D_BOUNDS void k_step3d(StepArgs a)
             }
         // Prefetched raw data of one plane zz: cur at zz + 4 (the queue's
         // next entry), prev and c at zz, and the halo cells of cur at zz.
-        // PFD planes are in flight ahead of the one being computed.
         struct Ahead {
             PT la[RY], pv[RY], yh[HH];
             PF cv[RY];
             T xh;
-            float gz;   // sponge factor of plane zz (loaded here, not after
-                        // the prefetch, so waiting for it never waits for
-                        // the next plane's loads)
+            float gz;   // sponge factor of plane zz (16-bit steps)
         };
         auto fetch = [&](int zz, Ahead &r) {
     #pragma unroll
@@ -510,67 +479,57 @@ __global__ FD_3D_BOUNDS void k_step3d(StepArgs a)
     #pragma unroll
             for (int hh = 0; hh < HH; ++hh) r.yh[hh] = ldhy(zz, hh);
             r.xh = ldhx(zz);
-            if constexpr (GZPF) r.gz = zz < nz ? a.gz[zz] : 0.0f;
+            if constexpr (LATE) r.gz = zz < nz ? a.gz[zz] : 0.0f;
         };
-        Ahead ah[PFD];
-    #pragma unroll
-        for (int d = 0; d < PFD; ++d) fetch(zb + d, ah[d]);
+        Ahead ah;
+        fetch(zb, ah);
         float bmax = 0.0f;
         Outgoing<T, VX> out[RY];
     #pragma unroll
         for (int j = 0; j < RY; ++j) out[j].ok = false;
 
-        // One plane.  At phase PH, plane z - 4 + k of the register queue sits in
-        // slot (k + PH) mod 9.  With FD_UNROLL9 the plane loop is unrolled 9
-        // times so the queue rotates by renaming; otherwise it runs at phase 0
-        // and the values shift down one slot per plane.
-        auto plane_step = [&](auto phase, int z) {
-            constexpr int PH = decltype(phase)::value;
+        // One plane: slot k of the register queue holds plane z - 4 + k; the
+        // values shift down one slot per plane.
+        auto plane_step = [&](int z) {
             float pc[RY][VX], cc[RY][VX], yhc[HH][VX];
     #pragma unroll
             for (int j = 0; j < RY; ++j)
     #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    q[j][(8 + PH) % 9][v] = decode_raw<ST>(ah[0].la[j].v[v]);
-                    pc[j][v] = decode_raw<ST>(ah[0].pv[j].v[v]);
-                    cc[j][v] = ah[0].cv[j].v[v];
+                    q[j][8][v] = decode_raw<ST>(ah.la[j].v[v]);
+                    pc[j][v] = decode_raw<ST>(ah.pv[j].v[v]);
+                    cc[j][v] = ah.cv[j].v[v];
                 }
     #pragma unroll
             for (int hh = 0; hh < HH; ++hh)
     #pragma unroll
-                for (int v = 0; v < VX; ++v) yhc[hh][v] = decode_raw<ST>(ah[0].yh[hh].v[v]);
-            const float xhc = decode_raw<ST>(ah[0].xh);
-            const float gzp = ah[0].gz;
-            // the previous plane's stores go out after the wait for this
-            // plane's data and just before the next prefetch
-            if constexpr (DEFER) {
+                for (int v = 0; v < VX; ++v) yhc[hh][v] = decode_raw<ST>(ah.yh[hh].v[v]);
+            const float xhc = decode_raw<ST>(ah.xh);
+            const float gzp = ah.gz;
+            // 16-bit: the previous plane's stores go out after the wait for
+            // this plane's data and just before the next prefetch
+            if constexpr (LATE) {
                 __builtin_amdgcn_sched_barrier(0);
     #pragma unroll
                 for (int j = 0; j < RY; ++j) flush<T, VX, MODE, true>(out[j]);
             }
-    #pragma unroll
-            for (int d = 0; d + 1 < PFD; ++d) ah[d] = ah[d + 1];
-            // unconditional (planes past the chunk are in bounds or read
-            // as zero): a skipped fetch would make the compiler keep and
-            // copy the previous plane's registers, and copying them waits
-            // for every outstanding memory operation
-            if (UNCOND || z + PFD < ze) fetch(z + PFD, ah[PFD - 1]);
+            if (LATE || z + 1 < ze) fetch(z + 1, ah);
             float *P = pl[z & 1];
     #pragma unroll
             for (int j = 0; j < RY; ++j)
     #pragma unroll
-                for (int v = 0; v < VX; ++v) P[(wy + NW * j + 4) * LW + 4 + lane * VX + v] = q[j][(4 + PH) % 9][v];
+                for (int v = 0; v < VX; ++v) P[(wy + NW * j + 4) * LW + 4 + lane * VX + v] = q[j][4][v];
     #pragma unroll
             for (int hh = 0; hh < HH; ++hh)
     #pragma unroll
                 for (int v = 0; v < VX; ++v) P[hyslot[hh] + v] = yhc[hh][v];
             if (hxl) P[hxslot] = xhc;
             __syncthreads();
-            const float gzz = GZPF ? gzp : a.gz[z];
+            const float gzz = LATE ? gzp : a.gz[z];
     #pragma unroll
             for (int j = 0; j < RY; ++j) {
                 float nw[VX], lp[VX], G[VX];
-                if constexpr (ST != kF32 && FD_H16_ARITH) {
+                if constexpr (ST != kF32) {
                     // 16-bit fields (VALU-bound): taps summed over the three
                     // axes before weighting, and the sponge factor's square
                     // taken per lane and per row, which saves instructions at
@@ -585,8 +544,8 @@ __global__ FD_3D_BOUNDS void k_step3d(StepArgs a)
     #pragma unroll
                         for (int k = 1; k <= 4; ++k)
                             sk[k - 1] = ((P[li - k] + P[li + k]) + (P[li - k * LW] + P[li + k * LW])) +
-                                        (qq[(4 - k + PH) % 9][v] + qq[(4 + k + PH) % 9][v]);
-                        const float ctr = qq[(4 + PH) % 9][v];
+                                        (qq[4 - k][v] + qq[4 + k][v]);
+                        const float ctr = qq[4][v];
                         const float lap = fmaf(3.0f * kA0, ctr,
                                                fmaf(kA4, sk[3], fmaf(kA3, sk[2], fmaf(kA2, sk[1], kA1 * sk[0]))));
                         G[v] = 0.0f;
@@ -602,14 +561,14 @@ __global__ FD_3D_BOUNDS void k_step3d(StepArgs a)
                     const float lyv = stencil_taps(P[li - 4 * LW], P[li - 3 * LW], P[li - 2 * LW],
                                                    P[li - LW], P[li + LW], P[li + 2 * LW],
                                                    P[li + 3 * LW], P[li + 4 * LW]);
-                    const float lz = stencil_taps(q[j][(0 + PH) % 9][v], q[j][(1 + PH) % 9][v],
-                                                  q[j][(2 + PH) % 9][v], q[j][(3 + PH) % 9][v],
-                                                  q[j][(5 + PH) % 9][v], q[j][(6 + PH) % 9][v],
-                                                  q[j][(7 + PH) % 9][v], q[j][(8 + PH) % 9][v]);
-                    const float lap = fmaf(3.0f * kA0, q[j][(4 + PH) % 9][v], lz + (lyv + lx));
+                    const float lz = stencil_taps(q[j][0][v], q[j][1][v],
+                                                  q[j][2][v], q[j][3][v],
+                                                  q[j][5][v], q[j][6][v],
+                                                  q[j][7][v], q[j][8][v]);
+                    const float lap = fmaf(3.0f * kA0, q[j][4][v], lz + (lyv + lx));
                     G[v] = (gzz * gyv[j]) * gxv[v];
-                    nw[v] = update<ST>(G[v], q[j][(4 + PH) % 9][v], cc[j][v], lap, pc[j][v], h);
-                    lp[v] = MODE == kFwdKeep ? q[j][(4 + PH) % 9][v] : lap;
+                    nw[v] = update<ST>(G[v], q[j][4][v], cc[j][v], lap, pc[j][v], h);
+                    lp[v] = MODE == kFwdKeep ? q[j][4][v] : lap;
                 }
                 }
                 if constexpr (OFF32)
@@ -620,33 +579,12 @@ __global__ FD_3D_BOUNDS void k_step3d(StepArgs a)
                     finish_cells<ST, VX, MODE, true, FULL>(a, h, z, yj[j], x0, lane_in && yin[j],
                                                            (size_t)z * pp + (size_t)yj[j] * px, (uint32_t)x0, nw,
                                                            lp, cc[j], G, inj, bmax, out[j]);
-                if constexpr (!DEFER) flush<T, VX, MODE, true>(out[j]);
+                if constexpr (!LATE) flush<T, VX, MODE, true>(out[j]);
             }
         };
         using std::integral_constant;
-    #if FD_UNROLL9
-        for (int z = zb; z < ze; z += 9) {
-            plane_step(integral_constant<int, 0>{}, z);
-            if (z + 1 >= ze) break;
-            plane_step(integral_constant<int, 1>{}, z + 1);
-            if (z + 2 >= ze) break;
-            plane_step(integral_constant<int, 2>{}, z + 2);
-            if (z + 3 >= ze) break;
-            plane_step(integral_constant<int, 3>{}, z + 3);
-            if (z + 4 >= ze) break;
-            plane_step(integral_constant<int, 4>{}, z + 4);
-            if (z + 5 >= ze) break;
-            plane_step(integral_constant<int, 5>{}, z + 5);
-            if (z + 6 >= ze) break;
-            plane_step(integral_constant<int, 6>{}, z + 6);
-            if (z + 7 >= ze) break;
-            plane_step(integral_constant<int, 7>{}, z + 7);
-            if (z + 8 >= ze) break;
-            plane_step(integral_constant<int, 8>{}, z + 8);
-        }
-    #else
         for (int z = zb; z < ze; ++z) {
-            plane_step(integral_constant<int, 0>{}, z);
+            plane_step(z);
     #pragma unroll
             for (int j = 0; j < RY; ++j)
     #pragma unroll
@@ -654,13 +592,12 @@ __global__ FD_3D_BOUNDS void k_step3d(StepArgs a)
     #pragma unroll
                     for (int v = 0; v < VX; ++v) q[j][k][v] = q[j][k + 1][v];
         }
-    #endif
     #pragma unroll
         for (int j = 0; j < RY; ++j) flush<T, VX, MODE, true>(out[j]);
         return bmax;
     };
     // (measured: a small gain with 16-bit fields, a small loss with FP32)
-    const bool full = FD_FULL_TILES && ST != kF32 && xb + TX <= nx && yb >= 4 && yb + TY + 4 <= ny;
+    const bool full = ST != kF32 && xb + TX <= nx && yb >= 4 && yb + TY + 4 <= ny;
     const float bmax = full ? tile(std::true_type{}) : tile(std::false_type{});
     if constexpr (ST != kF32)
         block_max_to<64 * NW>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax * h.sn, red);
@@ -910,14 +847,7 @@ hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, i
 #ifndef FD_3D_NW16
 #define FD_3D_NW16 4
 #endif
-#ifndef FD_3D_PF32
-#define FD_3D_PF32 1
-#endif
-#ifndef FD_3D_PF16
-#define FD_3D_PF16 1
-#endif
 constexpr int k3dVX32 = FD_3D_VX32, k3dRY32 = FD_3D_RY32;   // FP32 fields
-constexpr int k3dPF32 = FD_3D_PF32, k3dPF16 = FD_3D_PF16;   // planes prefetched
 constexpr int k3dVX16 = FD_3D_VX16, k3dRY16 = FD_3D_RY16;   // 16-bit fields
 constexpr int kBatchVX = 2;
 
@@ -934,15 +864,15 @@ static int64_t resident_blocks_3d(int storage)
         if (e == hipSuccess) {
             if (storage == kF32)
                 e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF32, k3dVX32, k3dRY32, FD_3D_NW32, kFwd, k3dPF32>),
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF32, k3dVX32, k3dRY32, FD_3D_NW32, kFwd>),
                     64 * FD_3D_NW32, 0);
             else if (storage == kF16)
                 e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd, k3dPF16>),
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd>),
                     64 * FD_3D_NW16, 0);
             else
                 e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kBF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd, k3dPF16>),
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kBF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd>),
                     64 * FD_3D_NW16, 0);
         }
         (void)hipGetLastError();
@@ -977,9 +907,6 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
         a.vx = VX;
         a.tiles_x = (a.nx + TX - 1) / TX;
         a.tiles_y = (a.ny + TY - 1) / TY;
-#ifdef FD_3D_ZC_FIXED
-        a.zc = FD_3D_ZC_FIXED;
-#else
         // Planes per block: a block streams zc planes after priming 8 halo
         // planes, and blocks run in ceil(blocks / resident) rounds, so the
         // time goes as ceil(blocks / resident) * (zc + 8).  The column is cut
@@ -989,16 +916,6 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
         const int64_t resident = resident_blocks_3d(storage);
         a.resident = (int32_t)std::min<int64_t>(resident, 1 << 30);
         int64_t best = -1;
-#ifdef FD_PLAN_POW2
-        for (int zc = 256; zc >= 16; zc >>= 1) {
-            const int64_t nb = cols * ((a.nz + zc - 1) / zc);
-            const int64_t cost = ((nb + resident - 1) / resident) * (std::min(zc, a.nz) + 8);
-            if (best < 0 || cost < best) {
-                best = cost;
-                a.zc = zc;
-            }
-        }
-#else
         for (int k = 1; k <= std::max(1, a.nz / 16); ++k) {
             const int zc = (a.nz + k - 1) / k;
             const int64_t nb = cols * ((a.nz + zc - 1) / zc);
@@ -1008,8 +925,6 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
                 a.zc = zc;
             }
         }
-#endif
-#endif
         a.tiles_z = (a.nz + a.zc - 1) / a.zc;
     }
 }
@@ -1018,10 +933,10 @@ template <int ST, int MODE>
 static void launch3d(const StepArgs &a, int nb, hipStream_t s)
 {
     if constexpr (ST == kF32)
-        hipLaunchKernelGGL((k_step3d<ST, k3dVX32, k3dRY32, FD_3D_NW32, MODE, k3dPF32>), dim3(nb),
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX32, k3dRY32, FD_3D_NW32, MODE>), dim3(nb),
                            dim3(64 * FD_3D_NW32), 0, s, a);
     else
-        hipLaunchKernelGGL((k_step3d<ST, k3dVX16, k3dRY16, FD_3D_NW16, MODE, k3dPF16>), dim3(nb),
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX16, k3dRY16, FD_3D_NW16, MODE>), dim3(nb),
                            dim3(64 * FD_3D_NW16), 0, s, a);
 }
 
