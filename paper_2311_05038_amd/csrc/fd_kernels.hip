@@ -331,22 +331,28 @@ __global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
 // --------------------------------------------------------------------------
 // 3D
 // --------------------------------------------------------------------------
-template <int ST, int VX, int RY, int NW, int MODE>
+// A wave covers RPW rows of the tile at once (64/RPW lanes per row, VX
+// cells per lane), so a lane's VX cells are contiguous in x; the block's NW
+// waves stack NW*RPW rows, and each thread handles RY such row groups.
+template <int ST, int VX, int RY, int NW, int RPW, int MODE>
 __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
 {
     using T = typename Stor<ST>::T;
     static_assert(NW == 2 || NW == 4 || NW == 8, "waves per block");
-    constexpr int TX = 64 * VX, TY = NW * RY, LW = TX + 8, LH = TY + 8, HH = 8 / NW;
+    static_assert(RPW == 1 || RPW == 2, "rows per wave");
+    static_assert(8 % (NW * RPW) == 0, "y-halo rows per wave");
+    constexpr int LPR = 64 / RPW;   // lanes per row
+    constexpr int TX = LPR * VX, TY = NW * RPW * RY, LW = TX + 8, LH = TY + 8, HH = 8 / (NW * RPW);
     __shared__ float pl[2][LH * LW];
     __shared__ float red[NW];
-    // wave index read as a wave-uniform value, so row tests become scalar branches
     const int lane = threadIdx.x & 63, wy = threadIdx.x >> 6;
+    const int col = lane % LPR, trow = wy * RPW + lane / LPR;   // thread's column and row
     const int nb = a.tiles_x * a.tiles_y * a.tiles_z;
     const int t = xcd_tile3d(blockIdx.x, nb, a.resident);
     const int tx = t % a.tiles_x;
     const int t2 = t / a.tiles_x;
     const int ty = t2 % a.tiles_y, tz = t2 / a.tiles_y;
-    const int xb = tx * TX, yb = ty * TY, x0 = xb + lane * VX;
+    const int xb = tx * TX, yb = ty * TY, x0 = xb + col * VX;
     const int zb = tz * a.zc, ze = min(zb + a.zc, a.nz);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t px = (size_t)a.px, pp = (size_t)ny * px;
@@ -369,7 +375,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
         float gyv[RY];
     #pragma unroll
         for (int j = 0; j < RY; ++j) {
-            yj[j] = yb + wy + NW * j;
+            yj[j] = yb + trow + NW * RPW * j;
             yin[j] = FULL || yj[j] < ny;
             gyv[j] = yin[j] ? a.gy[yj[j]] : 0.0f;
         }
@@ -380,16 +386,17 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
             gxv2[v] = gxv[v] * gxv[v];
         }
 
-        // y-halo rows handled by this thread: k = wy + NW hh, hh < 8 / NW.
+        // y-halo rows handled by this thread: k = (wy + NW hh) RPW + its row
+        // within the wave, hh < 8 / (NW RPW).
         int hy[HH], hyslot[HH];
         bool hyv[HH];
     #pragma unroll
         for (int hh = 0; hh < HH; ++hh) {
-            const int k = wy + NW * hh;
+            const int k = (wy + NW * hh) * RPW + lane / LPR;
             const int ly = k < 4 ? k - 4 : TY + k - 4;
             hy[hh] = yb + ly;
             hyv[hh] = FULL || (hy[hh] >= 0 && hy[hh] < ny && lane_in);
-            hyslot[hh] = (ly + 4) * LW + 4 + lane * VX;
+            hyslot[hh] = (ly + 4) * LW + 4 + col * VX;
         }
         // x-halo cell handled by this thread (threads < 8 TY).
         const bool hxl = threadIdx.x < 8 * TY;
@@ -518,7 +525,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
     #pragma unroll
             for (int j = 0; j < RY; ++j)
     #pragma unroll
-                for (int v = 0; v < VX; ++v) P[(wy + NW * j + 4) * LW + 4 + lane * VX + v] = q[j][4][v];
+                for (int v = 0; v < VX; ++v) P[(trow + NW * RPW * j + 4) * LW + 4 + col * VX + v] = q[j][4][v];
     #pragma unroll
             for (int hh = 0; hh < HH; ++hh)
     #pragma unroll
@@ -538,7 +545,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                     const float r1 = gr * h.sc, r2 = (gr * gr) * h.sp;
     #pragma unroll
                     for (int v = 0; v < VX; ++v) {
-                        const int li = (wy + NW * j + 4) * LW + 4 + lane * VX + v;
+                        const int li = (trow + NW * RPW * j + 4) * LW + 4 + col * VX + v;
                         const float(&qq)[9][VX] = q[j];
                         float sk[4];
     #pragma unroll
@@ -555,7 +562,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                 } else {
     #pragma unroll
                 for (int v = 0; v < VX; ++v) {
-                    const int li = (wy + NW * j + 4) * LW + 4 + lane * VX + v;
+                    const int li = (trow + NW * RPW * j + 4) * LW + 4 + col * VX + v;
                     const float lx = stencil_taps(P[li - 4], P[li - 3], P[li - 2], P[li - 1], P[li + 1],
                                                   P[li + 2], P[li + 3], P[li + 4]);
                     const float lyv = stencil_taps(P[li - 4 * LW], P[li - 3 * LW], P[li - 2 * LW],
@@ -827,8 +834,11 @@ hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, i
     return hipGetLastError();
 }
 
-// Tile shapes.  2D: one wave, 64*VX columns by zc rows.  3D: four waves,
-// (64*VX) x (4*RY) by zc planes.  (Overridable at build time for tuning.)
+// Tile shapes.  2D: one wave, 64*VX columns by zc rows.  3D: NW waves of
+// RPW rows each, (64/RPW*VX) x (NW*RPW*RY) cells by zc planes: FP32 fields
+// 256x8 (4 cells x 2 rows per lane), 16-bit fields 128x8 (4 cells x 1 row per
+// lane, two rows per wave: half the y-halo loads of a 256x4 tile, measured
+// 568 -> 554 us at 768x768x512 BF16).  (Overridable at build time for tuning.)
 #ifndef FD_3D_VX32
 #define FD_3D_VX32 4
 #endif
@@ -847,6 +857,12 @@ hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, i
 #ifndef FD_3D_NW16
 #define FD_3D_NW16 4
 #endif
+#ifndef FD_3D_RPW32
+#define FD_3D_RPW32 1
+#endif
+#ifndef FD_3D_RPW16
+#define FD_3D_RPW16 2
+#endif
 constexpr int k3dVX32 = FD_3D_VX32, k3dRY32 = FD_3D_RY32;   // FP32 fields
 constexpr int k3dVX16 = FD_3D_VX16, k3dRY16 = FD_3D_RY16;   // 16-bit fields
 constexpr int kBatchVX = 2;
@@ -864,15 +880,15 @@ static int64_t resident_blocks_3d(int storage)
         if (e == hipSuccess) {
             if (storage == kF32)
                 e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF32, k3dVX32, k3dRY32, FD_3D_NW32, kFwd>),
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF32, k3dVX32, k3dRY32, FD_3D_NW32, FD_3D_RPW32, kFwd>),
                     64 * FD_3D_NW32, 0);
             else if (storage == kF16)
                 e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd>),
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF16, k3dVX16, k3dRY16, FD_3D_NW16, FD_3D_RPW16, kFwd>),
                     64 * FD_3D_NW16, 0);
             else
                 e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kBF16, k3dVX16, k3dRY16, FD_3D_NW16, kFwd>),
+                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kBF16, k3dVX16, k3dRY16, FD_3D_NW16, FD_3D_RPW16, kFwd>),
                     64 * FD_3D_NW16, 0);
         }
         (void)hipGetLastError();
@@ -881,8 +897,9 @@ static int64_t resident_blocks_3d(int storage)
     return cache[k];
 }
 
-// Tile shapes.  3D: NW waves, (64 VX) x (NW RY) cells by zc planes (the
-// defaults come from a sweep of shapes on the 512^3 and 768x768x512 grids).
+// Tile shapes.  3D: NW waves of RPW rows, (64/RPW VX) x (NW RPW RY) cells by
+// zc planes (the defaults come from a sweep of shapes on the 512^3 and
+// 768x768x512 grids).
 // 2D: one wave, 64 VX columns by zc rows; the widest tile and tallest chunk
 // that still give >= 2048 blocks (8 per CU) are taken from
 // (VX, zc) = (2, 16), (2, 8), (1, 8), (1, 4).
@@ -903,7 +920,8 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
         const int VX = storage == kF32 ? k3dVX32 : k3dVX16;
         const int RY = storage == kF32 ? k3dRY32 : k3dRY16;
         const int NW = storage == kF32 ? FD_3D_NW32 : FD_3D_NW16;
-        const int TX = 64 * VX, TY = NW * RY;
+        const int RPW = storage == kF32 ? FD_3D_RPW32 : FD_3D_RPW16;
+        const int TX = 64 / RPW * VX, TY = NW * RPW * RY;
         a.vx = VX;
         a.tiles_x = (a.nx + TX - 1) / TX;
         a.tiles_y = (a.ny + TY - 1) / TY;
@@ -933,10 +951,10 @@ template <int ST, int MODE>
 static void launch3d(const StepArgs &a, int nb, hipStream_t s)
 {
     if constexpr (ST == kF32)
-        hipLaunchKernelGGL((k_step3d<ST, k3dVX32, k3dRY32, FD_3D_NW32, MODE>), dim3(nb),
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX32, k3dRY32, FD_3D_NW32, FD_3D_RPW32, MODE>), dim3(nb),
                            dim3(64 * FD_3D_NW32), 0, s, a);
     else
-        hipLaunchKernelGGL((k_step3d<ST, k3dVX16, k3dRY16, FD_3D_NW16, MODE>), dim3(nb),
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX16, k3dRY16, FD_3D_NW16, FD_3D_RPW16, MODE>), dim3(nb),
                            dim3(64 * FD_3D_NW16), 0, s, a);
 }
 
