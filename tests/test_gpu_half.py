@@ -28,7 +28,10 @@ FP64_TOL = {1: 1e-2, 2: 8e-2}
 
 
 def _cases():
-    return [fi.surface2d(70, 133, 200, seed=12), fi.layered3d(nx=72, ny=40, nz=45, nt=70)]
+    # case 2 is wide and deep enough for whole interior tiles (the 3D kernels'
+    # unchecked path), with ragged tiles at its edges
+    return [fi.surface2d(70, 133, 200, seed=12), fi.layered3d(nx=72, ny=40, nz=45, nt=70),
+            fi.layered3d(nx=300, ny=44, nz=36, nt=60)]
 
 
 def _start_state(p, k):
@@ -47,7 +50,7 @@ def _ulp_of(x, storage, e):
 
 
 @pytest.mark.parametrize("storage", [1, 2])
-@pytest.mark.parametrize("case", [0, 1])
+@pytest.mark.parametrize("case", [0, 1, 2])
 @pytest.mark.parametrize("nsteps", [1, 3])
 def test_code_level_parity_from_identical_states(storage, case, nsteps):
     import paper_2311_05038_amd as fd
@@ -100,7 +103,7 @@ def test_set_get_round_trip_matches_encoder(storage):
 
 
 @pytest.mark.parametrize("storage", [1, 2])
-@pytest.mark.parametrize("case", [0, 1])
+@pytest.mark.parametrize("case", [0, 1, 2])
 def test_whole_shot_error_against_fp64_is_bounded(storage, case):
     p = _cases()[case]
     print(f"case {p.name} storage={storage}", flush=True)
