@@ -277,7 +277,7 @@ def traffic_from_profiles(kernel_tag: str):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(nsteps: int = 16):
+def cpu_baseline(nsteps: int = 48):
     """The FP64 oracle on the same 512^3 model for a few steps."""
     import oracle
     import fd_inputs as fi

@@ -90,7 +90,7 @@ int64_t n_ckpt(int64_t nt, int32_t every) { return (nt + every - 1) / every; }
 
 size_t adjoint_work_bytes(const Layout &L, int32_t every)
 {
-    // recompute state (2) + L w history (every) + adjoint fields (2) + FP64 sum
+    // recompute state (2) + history fields (every) + adjoint fields (2) + FP64 sum
     return 2 * L.f32field + (size_t)every * L.f32field + 2 * L.f32field +
            align_up(L.npad * 8);
 }
@@ -116,7 +116,7 @@ fd_status check_grid(const fd_grid *g)
         return fail(FD_ERR_INVALID_ARG, "unknown storage kind %d", g->storage);
     const double cells = (double)g->nz * (double)g->ny * (double)((g->nx + 63) / 64 * 64);
     if (cells > 4.0e9) return fail(FD_ERR_INVALID_ARG, "grid too large");
-    // the 3D kernels address a plane with 32-bit byte offsets
+    // the 16-bit 3D kernels address a plane with 32-bit byte offsets
     if ((double)g->ny * (double)((g->nx + 63) / 64 * 64) >= 1073741824.0)
         return fail(FD_ERR_INVALID_ARG, "an x-y plane must hold fewer than 2^30 cells");
     return FD_OK;

@@ -5,10 +5,11 @@
 //   9 rows z-4..z+4 in registers, and the x-neighbours come from one LDS row
 //   (plus 4 halo cells each side).  One HBM read of cur/prev/c and one write
 //   per cell and step (16 B/cell in FP32, 10 B with 16-bit fields).
-// 3D (z, y, x): 4 waves per block.  A block owns a (64*VX) x (4*RY) tile of
-//   the x-y plane and a chunk of `zc` planes; lanes stream along z (the slow
-//   axis) with a 9-deep register queue per cell, and x/y neighbours come from
-//   a double-buffered LDS copy of the current plane with a 4-cell halo.
+// 3D (z, y, x): NW waves per block.  A block owns a tile of the x-y plane
+//   (256x8 cells for FP32 fields, 128x8 for 16-bit) and a chunk of `zc`
+//   planes; lanes stream along z (the slow axis) with a 9-deep register queue
+//   per cell, and x/y neighbours come from a double-buffered LDS copy of the
+//   current plane with a 4-cell halo.
 // Both follow the fused step of arXiv 2311.05038, Section 7 (Listing 3's
 // add_source, fd_pzz, fd_pxx, fd_time and swap in one pass).
 #include <algorithm>
@@ -38,12 +39,9 @@ namespace fdk {
 // --------------------------------------------------------------------------
 // Epilogue shared by 2D and 3D: receivers, source, padding, store.
 // --------------------------------------------------------------------------
-// A row's outgoing values, stored one plane (row) later: the stores are then
-// issued right before the next prefetch instead of right after the compute.
-// Vector loads and stores share one completion counter and a wait for a
-// load also waits for every store issued after it, so a store issued late
-// would make the next plane's wait for its prefetched data wait for that
-// store's round trip as well.
+// A row's outgoing values.  The 16-bit steps store them one plane (row)
+// later, right before the next prefetch (see the ordering note above); the
+// FP32 steps store them at once.
 template <typename T, int VX>
 struct Outgoing {
     Pack<T, VX> o;
