@@ -197,7 +197,7 @@ def grf_velocity(shape: Tuple[int, ...], seed: int, mean: float = 3000.0,
         bshape = [1] * len(shape)
         bshape[ax] = g.size
         spec *= g.reshape(bshape)
-    f = np.fft.irfftn(spec, s=shape)
+    f = np.fft.irfftn(spec, s=shape, axes=tuple(range(len(shape))))
     f = (f - f.mean()) / f.std()
     return np.clip(mean + std * f, vmin, vmax).astype(np.float32)
 

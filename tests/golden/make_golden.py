@@ -14,7 +14,12 @@ For adjoint2d_1024 (the 1024^2 / 2000-step gradient model, shot 0, start
 model v0, a seeded N(0,1) adjoint source r stored as FP32 in the file) the
 FP64 velocity gradient is stored the same way (cells, 16^2 block sums, norm).
 
+For serving2d_2048x4096 (one shot of the serving stream's largest grid,
+1000 steps) the traces of every 16th receiver, 8192 final cells, 16^2 block
+sums and the norms are stored.
+
 Usage:  python tests/golden/make_golden.py layered3d_512 [precision3d_768] [adjoint2d_1024]
+        [serving2d_2048x4096]
 """
 from __future__ import annotations
 
@@ -72,9 +77,38 @@ def make_adjoint(name: str) -> str:
     return path
 
 
+def serving_shot() -> fi.Problem:
+    """The largest grid of the serving stream's range (2048 x 4096, 1000
+    steps, random-field velocity): one shot, as the batched kernel runs it."""
+    return fi.surface2d(2048, 4096, 1000, seed=5050, name="serving2d_2048x4096")
+
+
+def make_serving(name: str) -> str:
+    t0 = time.time()
+    p = serving_shot()
+    v = p.velocity()
+    out = oracle.forward(oracle.grid_of(p), v.reshape(p.nz, 1, p.nx), p.wavelet(), p.nt, p.src,
+                         p.rec_index())
+    cur = out["cur"].reshape(p.nz, p.nx)
+    traces_idx = np.arange(0, p.receivers.count, 16).astype(np.int64)
+    rng = np.random.default_rng(1234)
+    cells_idx = rng.integers(0, p.ncells, 8192).astype(np.int64)
+    b = 16
+    blocks = cur.reshape(p.nz // b, b, p.nx // b, b).sum(axis=(1, 3))
+    path = os.path.join(HERE, f"{name}.npz")
+    np.savez_compressed(path, traces_idx=traces_idx, traces=out["traces"][:, traces_idx],
+                        cells_idx=cells_idx, cells=cur.ravel()[cells_idx], blocks=blocks,
+                        trace_norm=np.linalg.norm(out["traces"]), field_norm=np.linalg.norm(cur),
+                        seconds=time.time() - t0)
+    print(name, "written in %.0f s" % (time.time() - t0), flush=True)
+    return path
+
+
 def make(name: str) -> str:
     if name == "adjoint2d_1024":
         return make_adjoint(name)
+    if name == "serving2d_2048x4096":
+        return make_serving(name)
     p = {"layered3d_512": fi.layered3d(), "precision3d_768": fi.precision3d()}[name]
     t0 = time.time()
     v = p.velocity()
