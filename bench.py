@@ -94,15 +94,17 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 20):
 
 def half_leg(nt: int = 2000):
     """16-bit storage vs FP32 on the 768x768x512 grid (same model, source,
-    receivers): Mcell-updates/s of one whole shot each."""
+    receivers): Mcell-updates/s of one whole shot each, with c in FP32
+    (10 B/cell) and in 16-bit fixed point (8 B/cell) for the 16-bit fields."""
     import torch
     import fd_inputs as fi
     from helpers import setup
     p = fi.precision3d(nt=nt)
     v = p.velocity()
     out = {}
-    for name, st in (("f32", 0), ("f16", 1), ("bf16", 2)):
-        model, state, shot = setup(p, v, storage=st)
+    for name, st, c16 in (("f32", 0, 0), ("f16", 1, 0), ("bf16", 2, 0), ("f16_c16", 1, 1),
+                          ("bf16_c16", 2, 1)):
+        model, state, shot = setup(p, v, storage=st, c_storage=c16)
         traces = torch.empty((p.nt, p.receivers.count), device="cuda")
         model.run_shot(state, shot, traces)     # warm-up shot
         torch.cuda.synchronize()
@@ -113,15 +115,15 @@ def half_leg(nt: int = 2000):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1)
-        bpc = 16 if st == 0 else 10
+        bpc = 16 if st == 0 else (8 if c16 else 10)
         out[name] = dict(mcell_per_s=round(p.ncells * p.nt / (ms * 1e-3) / 1e6, 1),
-                         ms_per_shot=round(ms, 2),
+                         ms_per_shot=round(ms, 2), bytes_per_cell=bpc,
                          alg_gbs=round(bpc * p.ncells * p.nt / (ms * 1e-3) / 1e9, 1))
         log(f"[bench] half leg {name}: {out[name]}")
         del model, state, shot, traces
         torch.cuda.empty_cache()
-    out["speedup_f16"] = round(out["f16"]["mcell_per_s"] / out["f32"]["mcell_per_s"], 3)
-    out["speedup_bf16"] = round(out["bf16"]["mcell_per_s"] / out["f32"]["mcell_per_s"], 3)
+    for name in ("f16", "bf16", "f16_c16", "bf16_c16"):
+        out["speedup_" + name] = round(out[name]["mcell_per_s"] / out["f32"]["mcell_per_s"], 3)
     out["workload"] = "precision3d 768x768x512, nt=2000"
     return out
 

@@ -59,6 +59,12 @@ typedef enum {
 } fd_status;
 
 typedef enum { FD_F32 = 0, FD_F16 = 1, FD_BF16 = 2 } fd_storage;
+/* Storage of the model term c = (v dt / dh)^2.  FD_C_FIXED16 (with 16-bit
+ * fields only) keeps c as unsigned 16-bit fixed point with one power-of-two
+ * scale, q = min(RNE(c 2^(16-e)), 65535) with e = floor(log2 max c) + 1, so
+ * the step reads 8 bytes per cell instead of 10; |c - q 2^(e-16)| is at
+ * most 2^(e-17) (c is first rounded to FP32 from the FP64 product). */
+typedef enum { FD_C_F32 = 0, FD_C_FIXED16 = 1 } fd_c_storage;
 typedef enum { FD_BC_ZERO = 0, FD_BC_PERIODIC = 1 } fd_bc;
 
 /* Sponge face bits. */
@@ -84,6 +90,7 @@ typedef struct {
     double sponge_alpha;   /* damping constant; <= 0 selects 0.3 / sponge_width */
     uint32_t sponge_faces; /* FD_FACE_* bits of the faces that damp */
     int32_t storage;       /* fd_storage of the wavefields (arithmetic is FP32) */
+    int32_t c_storage;     /* fd_c_storage of c; FD_C_FIXED16 needs 16-bit fields */
 } fd_grid;
 
 /* A regular receiver array: cells (z0 + i*dz, y0 + j*dy, x0 + k*dx) for

@@ -79,7 +79,8 @@ def lib():
         L.or_adjoint.restype = ctypes.c_int
         L.or_image.argtypes = [P, P, P, i64, i64, i64, P, P, P]
         L.or_image.restype = ctypes.c_int
-        L.or_forward_half.argtypes = [P, ctypes.c_int, P, P, i64, i64, i64, P, P, P, P, P]
+        L.or_forward_half.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, i64, i64, i64, P, P, P, P, P]
+        L.or_c_fixed16.argtypes = [P, i64, P, P, ctypes.c_int]
         L.or_forward_half.restype = ctypes.c_int
         L.or_encode_array.argtypes = [ctypes.c_int, P, P, i64]
         L.or_decode_array.argtypes = [ctypes.c_int, P, P, i64]
@@ -196,9 +197,10 @@ def image(grid: OrGrid, v: np.ndarray, wavelet: np.ndarray, nt: int, src, rec_in
 
 
 def forward_half(grid: OrGrid, storage: int, v: np.ndarray, wavelet: np.ndarray, nt: int,
-                 src, rec_index, init_prev=None, init_cur=None):
+                 src, rec_index, init_prev=None, init_cur=None, c_fixed16: bool = False):
     """16-bit storage emulation (storage 1 = binary16, 2 = bfloat16).
-    init_prev/init_cur (FP32) replace the start state and its s[0] addition."""
+    init_prev/init_cur (FP32) replace the start state and its s[0] addition;
+    c_fixed16 holds c in 16-bit fixed point (c_fixed16())."""
     v = np.ascontiguousarray(v, dtype=np.float32)
     ip = None if init_prev is None else np.ascontiguousarray(init_prev, dtype=np.float32)
     ic = None if init_cur is None else np.ascontiguousarray(init_cur, dtype=np.float32)
@@ -206,12 +208,22 @@ def forward_half(grid: OrGrid, storage: int, v: np.ndarray, wavelet: np.ndarray,
     rec = np.ascontiguousarray(rec_index, dtype=np.int64)
     traces = np.zeros((nt, rec.size), dtype=np.float32)
     cur = np.empty(v.shape, dtype=np.float32)
-    rc = lib().or_forward_half(ctypes.byref(grid), storage, _p(v), _p(wavelet), nt,
+    rc = lib().or_forward_half(ctypes.byref(grid), storage, int(bool(c_fixed16)), _p(v), _p(wavelet), nt,
                                _src_linear(grid, src), rec.size, _p(rec), _p(ip), _p(ic),
                                _p(traces), _p(cur))
     if rc != 0:
         raise MemoryError("oracle forward_half: allocation failed")
     return dict(traces=traces, cur=cur)
+
+
+def c_fixed16(c: np.ndarray):
+    """c (FP32) as 16-bit unsigned fixed point with one power-of-two scale:
+    returns (codes, e, decoded) with decoded = codes * 2^(e-16) in FP32."""
+    c = np.array(c, dtype=np.float32, copy=True, order="C")
+    q = np.empty(c.shape, dtype=np.uint16)
+    e = ctypes.c_int32(0)
+    lib().or_c_fixed16(_p(c), c.size, _p(q), ctypes.byref(e), 1)
+    return q, int(e.value), c
 
 
 def encode(storage: int, x: np.ndarray) -> np.ndarray:

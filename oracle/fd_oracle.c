@@ -402,6 +402,35 @@ static int32_t storage_exponent(float m)
 }
 
 /*
+ * The model term c = (v dt/dh)^2 held as unsigned 16-bit fixed point with one
+ * power-of-two scale (the 16-bit storage form's option to store the model in
+ * 16 bits as well): with M the largest c, e is the exponent with
+ * 2^(e-1) <= M < 2^e, each code is the integer nearest c 2^(16-e) (ties to
+ * even), capped at 65535, and stands for code * 2^(e-16).  The rounding
+ * decision is taken on the FP32 value of c, as the kernels take it.  Writes
+ * the codes to q (may be NULL) and e to *e; replaces c by its decoded value
+ * when `decode_in_place` is set.
+ */
+void or_c_fixed16(float *c, int64_t n, uint16_t *q, int32_t *e, int decode_in_place)
+{
+    float M = 0.0f;
+    for (int64_t i = 0; i < n; ++i)
+        if (c[i] > M) M = c[i];
+    int ex = 0;
+    frexpf(M, &ex); /* M = f 2^ex, 1/2 <= f < 1 */
+    *e = ex;
+    for (int64_t i = 0; i < n; ++i) {
+        double t = ldexp((double)c[i], 16 - ex); /* exact */
+        double k = floor(t);
+        double frac = t - k;
+        if (frac > 0.5 || (frac == 0.5 && fmod(k, 2.0) != 0.0)) k += 1.0;
+        if (k > 65535.0) k = 65535.0;
+        if (q) q[i] = (uint16_t)k;
+        if (decode_in_place) c[i] = (float)ldexp(k, ex - 16);
+    }
+}
+
+/*
  * The 16-bit storage form of or_forward.  Arithmetic in FP32, the order of
  * the terms as in or_forward.  Per step n:
  *   decode cur, prev; lap = L(cur); x = G (2 cur + c lap) - G^2 prev;
@@ -413,11 +442,12 @@ static int32_t storage_exponent(float m)
  * (init_prev, init_cur) instead, the start state is those FP32 fields, each
  * stored with exponent floor(log2 max|field|) - 11, and no s[0] is added.
  * c and G are the FP64 setup rounded to FP32, G as a product of FP32 axis
- * profiles (z, y, x order).
+ * profiles (z, y, x order); with c_fixed16 set, c then takes its 16-bit
+ * fixed-point value (or_c_fixed16).
  */
-int or_forward_half(const or_grid *g, int storage, const float *v, const float *wavelet,
-                    int64_t nt, int64_t src, int64_t nrec, const int64_t *rec,
-                    const float *init_prev, const float *init_cur,
+int or_forward_half(const or_grid *g, int storage, int c_fixed16, const float *v,
+                    const float *wavelet, int64_t nt, int64_t src, int64_t nrec,
+                    const int64_t *rec, const float *init_prev, const float *init_cur,
                     float *traces, float *final_cur)
 {
     const int64_t N = g->nz * g->ny * g->nx;
@@ -448,6 +478,10 @@ int or_forward_half(const or_grid *g, int storage, const float *v, const float *
                 c[i] = (float)(q * q);
                 G[i] = ((float)gz[z] * (float)gy[y]) * (float)gx[xx];
             }
+    if (c_fixed16) {
+        int32_t ec16;
+        or_c_fixed16(c, N, NULL, &ec16, 1);
+    }
     double a64[9];
     or_coefficients(g->radius, a64);
     float a[9];

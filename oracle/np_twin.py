@@ -199,13 +199,19 @@ class Twin:
             ybar2, ybar1 = ybar1, ybar
         return gc
 
-    def forward_half(self, wavelet, nt, storage: int):
+    def forward_half(self, wavelet, nt, storage: int, c_fixed16: bool = False):
         """FP32 arithmetic with 16-bit storage and power-of-two field scales.
 
         storage 1: numpy float16 (IEEE binary16, round to nearest even);
-        storage 2: bfloat16 by round-to-nearest-even on the FP32 bit pattern."""
+        storage 2: bfloat16 by round-to-nearest-even on the FP32 bit pattern.
+        c_fixed16: c replaced by its 16-bit fixed-point value (codes
+        rint(c 2^(16-e)), at most 65535, with 2^(e-1) <= max c < 2^e)."""
         f32 = np.float32
         c = ((self.v * self.p.dt / self.p.dh) ** 2).astype(f32)
+        if c_fixed16:
+            e = int(np.frexp(c.max())[1])
+            codes = np.minimum(np.rint(c.astype(np.float64) * 2.0 ** (16 - e)), 65535.0)
+            c = (codes * 2.0 ** (e - 16)).astype(f32)
         shape = self.p.shape
         # axis profiles rounded to FP32, multiplied in z, y, x order
         axes_bits = [(0, 1)] + ([(2, 3)] if len(shape) == 3 else []) + [(4, 5)]

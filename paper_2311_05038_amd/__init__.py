@@ -21,11 +21,11 @@ from typing import Optional, Sequence
 import torch
 
 from . import _abi
-from ._abi import (FDError, FD_BF16, FD_F16, FD_F32, FD_BATCH_MAX, fd_batch_item, fd_grid,
-                   fd_receivers, fd_shot, fd_sizes)
+from ._abi import (FDError, FD_BF16, FD_C_F32, FD_C_FIXED16, FD_F16, FD_F32, FD_BATCH_MAX,
+                   fd_batch_item, fd_grid, fd_receivers, fd_shot, fd_sizes)
 
 __all__ = ["Grid", "Receivers", "Shot", "Model", "State", "FDError", "FD_F32", "FD_F16",
-           "FD_BF16", "step_batch", "ensure_built"]
+           "FD_BF16", "FD_C_F32", "FD_C_FIXED16", "step_batch", "ensure_built"]
 
 FACES_NO_TOP = 0x3E
 
@@ -60,6 +60,7 @@ class Grid:
     sponge_alpha: float = 0.0
     sponge_faces: int = FACES_NO_TOP
     storage: int = FD_F32
+    c_storage: int = FD_C_F32
     radius: int = 4
     bc: int = 0
 
@@ -67,7 +68,8 @@ class Grid:
         return fd_grid(ndim=self.ndim, radius=self.radius, bc=self.bc,
                        sponge_width=self.sponge_width, nz=self.nz, ny=self.ny, nx=self.nx,
                        dh=self.dh, dt=self.dt, sponge_alpha=self.sponge_alpha,
-                       sponge_faces=self.sponge_faces, storage=self.storage)
+                       sponge_faces=self.sponge_faces, storage=self.storage,
+                       c_storage=self.c_storage)
 
     @property
     def shape(self):

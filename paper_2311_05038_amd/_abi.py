@@ -20,6 +20,7 @@ FD_ERR_OUT_OF_MEMORY = 3
 FD_ERR_DEVICE = 4
 FD_ERR_UNSUPPORTED = 5
 FD_F32, FD_F16, FD_BF16 = 0, 1, 2
+FD_C_F32, FD_C_FIXED16 = 0, 1
 FD_BC_ZERO, FD_BC_PERIODIC = 0, 1
 FD_BATCH_MAX = 16
 
@@ -32,7 +33,7 @@ class fd_grid(ctypes.Structure):
                 ("sponge_width", ctypes.c_int32), ("nz", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("nx", ctypes.c_int64), ("dh", ctypes.c_double), ("dt", ctypes.c_double),
                 ("sponge_alpha", ctypes.c_double), ("sponge_faces", ctypes.c_uint32),
-                ("storage", ctypes.c_int32)]
+                ("storage", ctypes.c_int32), ("c_storage", ctypes.c_int32)]
 
 
 class fd_receivers(ctypes.Structure):

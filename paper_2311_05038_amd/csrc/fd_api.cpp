@@ -49,13 +49,14 @@ constexpr double kSymbolMax = 4096.0 / 630.0;
 constexpr int64_t kMaxDim = (int64_t)1 << 30;
 
 struct Layout {
-    int32_t ndim, storage;
+    int32_t ndim, storage, c_storage;
     int64_t nz, ny, nx;
     int32_t px;        // row pitch in elements (multiple of 64)
     size_t npad;       // nz * ny * px
     size_t elem;       // bytes per stored field element
     size_t field;      // bytes of one stored field, aligned
     size_t f32field;   // bytes of one FP32 padded field, aligned
+    size_t cfield;     // bytes of the stored c (FP32 or 16-bit fixed point), aligned
     size_t c_off, gz_off, gy_off, gx_off, scratch_off, model_bytes;
     size_t state_bytes, meta_off;
 };
@@ -65,6 +66,7 @@ Layout make_layout(const fd_grid &g)
     Layout L{};
     L.ndim = g.ndim;
     L.storage = g.storage;
+    L.c_storage = g.c_storage;
     L.nz = g.nz;
     L.ny = g.ny;
     L.nx = g.nx;
@@ -73,8 +75,9 @@ Layout make_layout(const fd_grid &g)
     L.elem = g.storage == FD_F32 ? 4 : 2;
     L.field = align_up(L.npad * L.elem);
     L.f32field = align_up(L.npad * 4);
+    L.cfield = g.c_storage == FD_C_FIXED16 ? align_up(L.npad * 2) : L.f32field;
     L.c_off = 0;
-    L.gz_off = L.c_off + L.f32field;
+    L.gz_off = L.c_off + L.cfield;
     L.gy_off = L.gz_off + align_up((size_t)g.nz * 4);
     L.gx_off = L.gy_off + align_up((size_t)g.ny * 4);
     L.scratch_off = L.gx_off + align_up((size_t)g.nx * 4);
@@ -114,6 +117,10 @@ fd_status check_grid(const fd_grid *g)
     if (!std::isfinite(g->sponge_alpha)) return fail(FD_ERR_INVALID_ARG, "sponge_alpha must be finite");
     if (g->storage != FD_F32 && g->storage != FD_F16 && g->storage != FD_BF16)
         return fail(FD_ERR_INVALID_ARG, "unknown storage kind %d", g->storage);
+    if (g->c_storage != FD_C_F32 && g->c_storage != FD_C_FIXED16)
+        return fail(FD_ERR_INVALID_ARG, "unknown c storage kind %d", g->c_storage);
+    if (g->c_storage == FD_C_FIXED16 && g->storage == FD_F32)
+        return fail(FD_ERR_UNSUPPORTED, "16-bit c is built for 16-bit fields only");
     const double cells = (double)g->nz * (double)g->ny * (double)((g->nx + 63) / 64 * 64);
     if (cells > 4.0e9) return fail(FD_ERR_INVALID_ARG, "grid too large");
     // the 16-bit 3D kernels address a plane with 32-bit byte offsets
@@ -127,7 +134,11 @@ fd_status check_grid(const fd_grid *g)
 struct fd_model {
     fd_grid grid;
     Layout L;
-    float *c, *gz, *gy, *gx;
+    float *c;          // FP32 c, or null when c is stored in 16-bit fixed point
+    uint16_t *c16;     // 16-bit fixed-point c (value c16 * c16_scale), or null
+    float c16_scale;   // 2^(e - 16)
+    float c16_inv;     // 2^(16 - e)
+    float *gz, *gy, *gx;
     uint32_t *scratch;
     float amp;  // dt^2 / h^D
 };
@@ -173,6 +184,9 @@ StepArgs base_args(const fd_model *m, const fd_shot *s)
     StepArgs a{};
     const Layout &L = m->L;
     a.c = m->c;
+    a.c16 = m->c16;
+    a.c16_scale = m->c16_scale;
+    a.c16_inv = m->c16_inv;
     a.gz = m->gz;
     a.gy = m->gy;
     a.gx = m->gx;
@@ -272,7 +286,11 @@ fd_status fd_create_model(const fd_grid *grid, const float *velocity, void *mode
         m->grid.sponge_alpha = 0.3 / m->grid.sponge_width;
     m->L = L;
     char *base = (char *)model_buf;
-    m->c = (float *)(base + L.c_off);
+    const bool fixed16 = L.c_storage == FD_C_FIXED16;
+    m->c = fixed16 ? nullptr : (float *)(base + L.c_off);
+    m->c16 = fixed16 ? (uint16_t *)(base + L.c_off) : nullptr;
+    m->c16_scale = 1.0f;
+    m->c16_inv = 1.0f;
     m->gz = (float *)(base + L.gz_off);
     m->gy = (float *)(base + L.gy_off);
     m->gx = (float *)(base + L.gx_off);
@@ -305,8 +323,10 @@ fd_status fd_create_model(const fd_grid *grid, const float *velocity, void *mode
     hipError_t e = hipMemcpyAsync(m->gz, gz.data(), gz.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(m->gy, gy.data(), gy.size() * 4, hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipMemcpyAsync(m->gx, gx.data(), gx.size() * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = fdk::launch_fill_u32(m->c, L.npad, 0u, s);
+    if (e == hipSuccess) e = fdk::launch_fill_u32((uint32_t *)(base + L.c_off), L.cfield / 4, 0u, s);
     if (e == hipSuccess) e = fdk::launch_fill_u32(m->scratch, 2, 0u, s);
+    // FP32 c, or (16-bit c) only the velocity range: the fixed-point scale
+    // depends on the largest c
     if (e == hipSuccess)
         e = fdk::launch_model_c(velocity, m->c, L.nz * L.ny, (int32_t)L.nx, L.px,
                                 grid->dt / grid->dh, m->scratch, s);
@@ -329,6 +349,23 @@ fd_status fd_create_model(const fd_grid *grid, const float *velocity, void *mode
         return fail(FD_ERR_UNSTABLE,
                     "unstable: vmax*dt/dh = %.6f exceeds the %dD limit %.6f", cfl, grid->ndim,
                     std::sqrt(4.0 / (grid->ndim * kSymbolMax)));
+    }
+    if (fixed16) {
+        // the largest c, rounded to FP32 exactly as the kernels round every c
+        // (the product is monotone in v), fixes e = floor(log2 cmax) + 1
+        const double qq = (double)vmax * (grid->dt / grid->dh);
+        const float cmax = (float)(qq * qq);
+        int ex = 0;
+        std::frexp(cmax, &ex);  // cmax = f 2^ex with f in [0.5, 1)
+        m->c16_scale = std::ldexp(1.0f, ex - 16);
+        m->c16_inv = std::ldexp(1.0f, 16 - ex);
+        e = fdk::launch_model_c16(velocity, m->c16, L.nz * L.ny, (int32_t)L.nx, L.px,
+                                  grid->dt / grid->dh, std::ldexp(1.0f, 16 - ex), s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) {
+            delete m;
+            return hip_fail(e, "fd_create_model");
+        }
     }
     *out = m;
     return ok();

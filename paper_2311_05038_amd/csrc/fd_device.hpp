@@ -60,7 +60,10 @@ struct RecBox {
 struct StepArgs {
     const void *cur;      // level n
     void *prev;           // level n-1 in, level n+1 out
-    const float *c;       // (v dt / h)^2, padded, zero in padding
+    const float *c;       // (v dt / h)^2, padded, zero in padding (FP32 c)
+    const uint16_t *c16;  // or 16-bit fixed point: c = c16 * c16_scale (else null)
+    float c16_scale;      // 2^(e - 16)
+    float c16_inv;        // 2^(16 - e)
     const float *gz, *gy, *gx;  // damping profiles (nz, ny, nx entries)
     int32_t nz, ny, nx, px;
     int32_t zc;           // planes (rows in 2D) per block

@@ -165,12 +165,15 @@ __device__ __forceinline__ float update(float G, float ctr, float c, float lap, 
 // --------------------------------------------------------------------------
 // 2D
 // --------------------------------------------------------------------------
-template <int ST, int VX, int MODE>
+// CQ: c is read as 16-bit fixed-point codes (16-bit fields, forward step).
+template <int ST, int VX, int MODE, bool CQ>
 __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
                                             float (*row)[64 * VX + 8], const HalfCtx &h,
                                             float inj, float &bmax)
 {
+    static_assert(!CQ || (ST != kF32 && MODE == kFwd), "16-bit c: 16-bit fields, forward step");
     using T = typename Stor<ST>::T;
+    using CT = std::conditional_t<CQ, uint16_t, float>;
     constexpr int TX = 64 * VX;
     const int lane = threadIdx.x & 63;
     const int xb = tx * TX;
@@ -201,7 +204,12 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
     // Loads return raw packs (zero outside the grid); values are decoded
     // where they are consumed, so a prefetch never waits for its own load.
     using PT = Pack<T, VX>;
-    using PF = Pack<float, VX>;
+    using PC = Pack<CT, VX>;
+    const CT *cbase;
+    if constexpr (CQ)
+        cbase = a.c16;
+    else
+        cbase = a.c;
     auto ld_cur = [&](int z) -> PT {
         PT p{};
         if (z >= 0 && z < nz && lane_in) p = ldp<T, VX>(cur + (size_t)z * px + x0);
@@ -212,9 +220,9 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
         if (z < nz && lane_in) p = ldp<T, VX>(prv + (size_t)z * px + x0);
         return p;
     };
-    auto ld_c = [&](int z) -> PF {
-        PF p{};
-        if (z < nz && lane_in) p = ldp<float, VX>(a.c + (size_t)z * px + x0);
+    auto ld_c = [&](int z) -> PC {
+        PC p{};
+        if (z < nz && lane_in) p = ldp<CT, VX>(cbase + (size_t)z * px + x0);
         return p;
     };
     auto ld_halo = [&](int z) -> T { return (hvalid && z < nz) ? cur[(size_t)z * px + hx] : (T)0; };
@@ -227,7 +235,7 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
         for (int v = 0; v < VX; ++v) q[k][v] = decode_raw<ST>(p.v[v]);
     }
     PT la = ld_cur(zb + 4), pv = ld_prev(zb);
-    PF cv = ld_c(zb);
+    PC cv = ld_c(zb);
     T hv = ld_halo(zb);
     // the row's sponge factor travels with the prefetch: a load issued after
     // it and waited for in the same row would also wait for the prefetch
@@ -242,7 +250,10 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
         for (int v = 0; v < VX; ++v) {
             q[8][v] = decode_raw<ST>(la.v[v]);
             pc[v] = decode_raw<ST>(pv.v[v]);
-            cc[v] = cv.v[v];
+            if constexpr (CQ)
+                cc[v] = (float)cv.v[v] * a.c16_scale;   // exact: a power-of-two scale
+            else
+                cc[v] = cv.v[v];
         }
         const float hc = decode_raw<ST>(hv);
         const float gzp = gn;
@@ -289,7 +300,7 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
     flush<T, VX, MODE, false>(out);
 }
 
-template <int ST, int VX, int MODE>
+template <int ST, int VX, int MODE, bool CQ>
 __global__ __launch_bounds__(64) void k_step2d(StepArgs a)
 {
     __shared__ float row[2][64 * VX + 8];
@@ -301,7 +312,7 @@ __global__ __launch_bounds__(64) void k_step2d(StepArgs a)
         if (a.n + 1 < a.nt) inj = a.amp * a.wavelet[a.n + 1];
     const HalfCtx h = half_prologue<ST>(a, inj, blockIdx.x == 0);
     float bmax = 0.0f;
-    step2d_tile<ST, VX, MODE>(a, tx, tz, row, h, inj, bmax);
+    step2d_tile<ST, VX, MODE, CQ>(a, tx, tz, row, h, inj, bmax);
     if constexpr (ST != kF32)
         block_max_to<64>(max_slot(a.meta, (int)((a.n + 1) & 3)), bmax * h.sn, nullptr);
 }
@@ -323,7 +334,7 @@ __global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
         if (a.n + 1 < a.nt) inj = a.amp * a.wavelet[a.n + 1];
     const HalfCtx h{1.0f, 1.0f, 1.0f, 1.0f};
     float bmax = 0.0f;
-    step2d_tile<kF32, VX, MODE>(a, tx, tz, row, h, inj, bmax);
+    step2d_tile<kF32, VX, MODE, false>(a, tx, tz, row, h, inj, bmax);
 }
 
 // --------------------------------------------------------------------------
@@ -332,10 +343,16 @@ __global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
 // A wave covers RPW rows of the tile at once (64/RPW lanes per row, VX
 // cells per lane), so a lane's VX cells are contiguous in x; the block's NW
 // waves stack NW*RPW rows, and each thread handles RY such row groups.
-template <int ST, int VX, int RY, int NW, int RPW, int MODE>
+// CQ: c is read as 16-bit fixed-point codes q (16-bit fields, forward step):
+// 2 P + c L P = s (2 P / s + q L P) with s = 2^(e-16), and s joins the
+// other power-of-two factors of the update (exact; the Laplacian keeps its
+// scale, which stays clear of FP32 subnormals with bit-moved binary16).
+template <int ST, int VX, int RY, int NW, int RPW, int MODE, bool CQ>
 __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
 {
+    static_assert(!CQ || (ST != kF32 && MODE == kFwd), "16-bit c: 16-bit fields, forward step");
     using T = typename Stor<ST>::T;
+    using CT = std::conditional_t<CQ, uint16_t, float>;
     static_assert(NW == 2 || NW == 4 || NW == 8, "waves per block");
     static_assert(RPW == 1 || RPW == 2, "rows per wave");
     static_assert(8 % (NW * RPW) == 0, "y-halo rows per wave");
@@ -429,7 +446,12 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
         // Loads return raw packs (zero outside the grid); values are decoded
         // where they are consumed, so a prefetch never waits for its own load.
         using PT = Pack<T, VX>;
-        using PF = Pack<float, VX>;
+        using PC = Pack<CT, VX>;
+        const CT *cbase;
+        if constexpr (CQ)
+            cbase = a.c16;
+        else
+            cbase = a.c;
         auto ld3 = [&](const T *base, int z, int j) -> PT {
             PT p{};
             if (z >= 0 && z < nz && (FULL || (yin[j] && lane_in)))
@@ -442,10 +464,10 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                 p = ldp_stream<T, VX>(addr(base, z, eo[j], yj[j], x0));
             return p;
         };
-        auto ldc3 = [&](int z, int j) -> PF {
-            PF p{};
+        auto ldc3 = [&](int z, int j) -> PC {
+            PC p{};
             if (z < nz && (FULL || (yin[j] && lane_in)))
-                p = ldp_stream<float, VX>(addr(a.c, z, eo[j], yj[j], x0));
+                p = ldp_stream<CT, VX>(addr(cbase, z, eo[j], yj[j], x0));
             return p;
         };
         auto ldhy = [&](int z, int hh) -> PT {
@@ -470,7 +492,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
         // next entry), prev and c at zz, and the halo cells of cur at zz.
         struct Ahead {
             PT la[RY], pv[RY], yh[HH];
-            PF cv[RY];
+            PC cv[RY];
             T xh;
             float gz;   // sponge factor of plane zz (16-bit steps)
         };
@@ -503,7 +525,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                 for (int v = 0; v < VX; ++v) {
                     q[j][8][v] = decode_raw<ST>(ah.la[j].v[v]);
                     pc[j][v] = decode_raw<ST>(ah.pv[j].v[v]);
-                    cc[j][v] = ah.cv[j].v[v];
+                    cc[j][v] = (float)ah.cv[j].v[v];
                 }
     #pragma unroll
             for (int hh = 0; hh < HH; ++hh)
@@ -540,7 +562,9 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                     // taken per lane and per row, which saves instructions at
                     // a different FP32 rounding order.
                     const float gr = gzz * gyv[j];
-                    const float r1 = gr * h.sc, r2 = (gr * gr) * h.sp;
+                    const float sc = CQ ? h.sc * a.c16_scale : h.sc;
+                    const float two = CQ ? 2.0f * a.c16_inv : 2.0f;
+                    const float r1 = gr * sc, r2 = (gr * gr) * h.sp;
     #pragma unroll
                     for (int v = 0; v < VX; ++v) {
                         const int li = (trow + NW * RPW * j + 4) * LW + 4 + col * VX + v;
@@ -554,7 +578,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                         const float lap = fmaf(3.0f * kA0, ctr,
                                                fmaf(kA4, sk[3], fmaf(kA3, sk[2], fmaf(kA2, sk[1], kA1 * sk[0]))));
                         G[v] = 0.0f;
-                        nw[v] = fmaf(gxv[v] * r1, fmaf(cc[j][v], lap, 2.0f * ctr), -(gxv2[v] * r2) * pc[j][v]);
+                        nw[v] = fmaf(gxv[v] * r1, fmaf(cc[j][v], lap, two * ctr), -(gxv2[v] * r2) * pc[j][v]);
                         lp[v] = lap;
                     }
                 } else {
@@ -618,8 +642,15 @@ __global__ void k_fill_u32(uint32_t *p, size_t n, uint32_t val)
     for (; i < n; i += stride) p[i] = val;
 }
 
-// c = (v dt/h)^2 rounded from FP64 to FP32, padded; also the velocity range
-// (max as float bits) and a flag for non-positive or non-finite values.
+// c = (v dt/h)^2 rounded from FP64 to FP32.
+__device__ __forceinline__ float model_c(float v, double r)
+{
+    const double qq = (double)v * r;
+    return (float)(qq * qq);
+}
+
+// c padded (skipped when c is null); also the velocity range (max as float
+// bits) and a flag for non-positive or non-finite values.
 __global__ void k_model_c(const float *__restrict__ v, float *__restrict__ c, int64_t nrows,
                           int32_t nx, int32_t px, double r, uint32_t *scratch)
 {
@@ -632,8 +663,7 @@ __global__ void k_model_c(const float *__restrict__ v, float *__restrict__ c, in
         const float vi = v[i];
         if (!(vi > 0.0f) || !(vi < 3.0e38f)) bad = 1;
         vmax = max(vmax, __float_as_uint(fabsf(vi)));
-        const double qq = (double)vi * r;
-        c[rw * (size_t)px + x] = (float)(qq * qq);
+        if (c != nullptr) c[rw * (size_t)px + x] = model_c(vi, r);
     }
     for (int off = 32; off >= 1; off >>= 1) {
         vmax = max(vmax, (uint32_t)__shfl_xor((int)vmax, off, 64));
@@ -642,6 +672,21 @@ __global__ void k_model_c(const float *__restrict__ v, float *__restrict__ c, in
     if ((threadIdx.x & 63) == 0) {
         atomicMax(&scratch[0], vmax);
         if (bad) atomicOr(&scratch[1], 1u);
+    }
+}
+
+// c in 16-bit unsigned fixed point: q = min(RNE(c 2^(16-e)), 65535), where
+// inv_scale = 2^(16-e) and c < 2^e for every cell (the product is exact).
+__global__ void k_model_c16(const float *__restrict__ v, uint16_t *__restrict__ c16, int64_t nrows,
+                            int32_t nx, int32_t px, double r, float inv_scale)
+{
+    const size_t total = (size_t)nrows * nx;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < total; i += stride) {
+        const size_t rw = i / (size_t)nx, x = i - rw * (size_t)nx;
+        const float q = fminf(rintf(model_c(v[i], r) * inv_scale), 65535.0f);
+        c16[rw * (size_t)px + x] = (uint16_t)q;
     }
 }
 
@@ -772,6 +817,14 @@ hipError_t launch_model_c(const float *v, float *c, int64_t nrows, int32_t nx, i
     return hipGetLastError();
 }
 
+hipError_t launch_model_c16(const float *v, uint16_t *c16, int64_t nrows, int32_t nx, int32_t px,
+                            double r, float inv_scale, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_model_c16, dim3(grid_blocks((size_t)nrows * nx, 256)), dim3(256), 0, s,
+                       v, c16, nrows, nx, px, r, inv_scale);
+    return hipGetLastError();
+}
+
 hipError_t launch_begin(int storage, void *cur, int64_t src_off, float amp,
                         const float *wavelet, int32_t *meta, hipStream_t s)
 {
@@ -865,29 +918,32 @@ constexpr int k3dVX32 = FD_3D_VX32, k3dRY32 = FD_3D_RY32;   // FP32 fields
 constexpr int k3dVX16 = FD_3D_VX16, k3dRY16 = FD_3D_RY16;   // 16-bit fields
 constexpr int kBatchVX = 2;
 
+// The 3D forward kernel of a storage kind (16-bit c or not).
+template <int ST, bool CQ>
+static const void *step3d_fwd_kernel()
+{
+    if constexpr (ST == kF32)
+        return reinterpret_cast<const void *>(&k_step3d<kF32, k3dVX32, k3dRY32, FD_3D_NW32, FD_3D_RPW32, kFwd, false>);
+    else
+        return reinterpret_cast<const void *>(&k_step3d<ST, k3dVX16, k3dRY16, FD_3D_NW16, FD_3D_RPW16, kFwd, CQ>);
+}
+
 // Blocks of the 3D forward kernel that fit on the device at once (queried
 // once per storage kind; the CU count times the occupancy per CU).
-static int64_t resident_blocks_3d(int storage)
+static int64_t resident_blocks_3d(int storage, bool cq)
 {
-    static int64_t cache[3] = {0, 0, 0};
-    const int k = storage == kF32 ? 0 : (storage == kF16 ? 1 : 2);
+    static int64_t cache[5] = {0, 0, 0, 0, 0};
+    const int k = storage == kF32 ? 0 : (storage == kF16 ? 1 : 2) + (cq ? 2 : 0);
     if (cache[k] == 0) {
         int dev = 0, cus = 0, per_cu = 0;
         hipError_t e = hipGetDevice(&dev);
         if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
         if (e == hipSuccess) {
-            if (storage == kF32)
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF32, k3dVX32, k3dRY32, FD_3D_NW32, FD_3D_RPW32, kFwd>),
-                    64 * FD_3D_NW32, 0);
-            else if (storage == kF16)
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kF16, k3dVX16, k3dRY16, FD_3D_NW16, FD_3D_RPW16, kFwd>),
-                    64 * FD_3D_NW16, 0);
-            else
-                e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
-                    &per_cu, reinterpret_cast<const void *>(&k_step3d<kBF16, k3dVX16, k3dRY16, FD_3D_NW16, FD_3D_RPW16, kFwd>),
-                    64 * FD_3D_NW16, 0);
+            const void *f = storage == kF32 ? step3d_fwd_kernel<kF32, false>()
+                            : storage == kF16 ? (cq ? step3d_fwd_kernel<kF16, true>() : step3d_fwd_kernel<kF16, false>())
+                                              : (cq ? step3d_fwd_kernel<kBF16, true>() : step3d_fwd_kernel<kBF16, false>());
+            const int threads = 64 * (storage == kF32 ? FD_3D_NW32 : FD_3D_NW16);
+            e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, f, threads, 0);
         }
         (void)hipGetLastError();
         cache[k] = (e == hipSuccess && cus > 0 && per_cu > 0) ? (int64_t)cus * per_cu : 512;
@@ -929,7 +985,7 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
         // into k equal chunks (zc = ceil(nz / k) >= 16); ties go to the
         // longer chunk (less halo traffic).
         const int64_t cols = (int64_t)a.tiles_x * a.tiles_y;
-        const int64_t resident = resident_blocks_3d(storage);
+        const int64_t resident = resident_blocks_3d(storage, a.c16 != nullptr);
         a.resident = (int32_t)std::min<int64_t>(resident, 1 << 30);
         int64_t best = -1;
         for (int k = 1; k <= std::max(1, a.nz / 16); ++k) {
@@ -945,14 +1001,14 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
     }
 }
 
-template <int ST, int MODE>
+template <int ST, int MODE, bool CQ = false>
 static void launch3d(const StepArgs &a, int nb, hipStream_t s)
 {
     if constexpr (ST == kF32)
-        hipLaunchKernelGGL((k_step3d<ST, k3dVX32, k3dRY32, FD_3D_NW32, FD_3D_RPW32, MODE>), dim3(nb),
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX32, k3dRY32, FD_3D_NW32, FD_3D_RPW32, MODE, false>), dim3(nb),
                            dim3(64 * FD_3D_NW32), 0, s, a);
     else
-        hipLaunchKernelGGL((k_step3d<ST, k3dVX16, k3dRY16, FD_3D_NW16, FD_3D_RPW16, MODE>), dim3(nb),
+        hipLaunchKernelGGL((k_step3d<ST, k3dVX16, k3dRY16, FD_3D_NW16, FD_3D_RPW16, MODE, CQ>), dim3(nb),
                            dim3(64 * FD_3D_NW16), 0, s, a);
 }
 
@@ -960,20 +1016,25 @@ template <int VX>
 static void launch2d(const StepArgs &a, int storage, int mode, int nb, hipStream_t s)
 {
     const dim3 g(nb), b(64);
+    const bool cq = a.c16 != nullptr;
     if (storage == kF32) {
-        if (mode == kFwd) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwd>), g, b, 0, s, a);
-        else if (mode == kFwdLap) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwdLap>), g, b, 0, s, a);
-        else if (mode == kFwdKeep) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwdKeep>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_step2d<kF32, VX, kAdj>), g, b, 0, s, a);
+        if (mode == kFwd) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwd, false>), g, b, 0, s, a);
+        else if (mode == kFwdLap) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwdLap, false>), g, b, 0, s, a);
+        else if (mode == kFwdKeep) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwdKeep, false>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_step2d<kF32, VX, kAdj, false>), g, b, 0, s, a);
     } else if (storage == kF16) {
-        hipLaunchKernelGGL((k_step2d<kF16, VX, kFwd>), g, b, 0, s, a);
+        if (cq) hipLaunchKernelGGL((k_step2d<kF16, VX, kFwd, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_step2d<kF16, VX, kFwd, false>), g, b, 0, s, a);
     } else {
-        hipLaunchKernelGGL((k_step2d<kBF16, VX, kFwd>), g, b, 0, s, a);
+        if (cq) hipLaunchKernelGGL((k_step2d<kBF16, VX, kFwd, true>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_step2d<kBF16, VX, kFwd, false>), g, b, 0, s, a);
     }
 }
 
 hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t s)
 {
+    // 16-bit c is built for the forward step on 16-bit fields only
+    if (a.c16 != nullptr && (storage == kF32 || mode != kFwd)) return hipErrorInvalidValue;
     plan_tiles(a, ndim, storage, false);
     const int nb = a.tiles_x * a.tiles_y * a.tiles_z;
     if (ndim == 2) {
@@ -986,9 +1047,11 @@ hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t 
             else if (mode == kFwdKeep) launch3d<kF32, kFwdKeep>(a, nb, s);
             else launch3d<kF32, kAdj>(a, nb, s);
         } else if (storage == kF16) {
-            launch3d<kF16, kFwd>(a, nb, s);
+            if (a.c16 != nullptr) launch3d<kF16, kFwd, true>(a, nb, s);
+            else launch3d<kF16, kFwd>(a, nb, s);
         } else {
-            launch3d<kBF16, kFwd>(a, nb, s);
+            if (a.c16 != nullptr) launch3d<kBF16, kFwd, true>(a, nb, s);
+            else launch3d<kBF16, kFwd>(a, nb, s);
         }
     }
     return hipGetLastError();

@@ -29,8 +29,13 @@ hipError_t launch_step_batch2d(Batch2D &b, int mode, hipStream_t s);
 hipError_t launch_routines(const StepArgs &a, int ndim, float *dzz, float *dxx, float *dyy,
                            hipStream_t s);
 hipError_t launch_fill_u32(void *p, size_t nwords, uint32_t val, hipStream_t s);
+// c = (v r)^2 into `c` (padded FP32; null: velocity range only), with the
+// largest |v| and a flag for bad velocities in scratch[0..1].
 hipError_t launch_model_c(const float *v, float *c, int64_t nrows, int32_t nx, int32_t px,
                           double r, uint32_t *scratch, hipStream_t s);
+// c as 16-bit fixed point: min(RNE(c inv_scale), 65535), padded.
+hipError_t launch_model_c16(const float *v, uint16_t *c16, int64_t nrows, int32_t nx, int32_t px,
+                            double r, float inv_scale, hipStream_t s);
 hipError_t launch_begin(int storage, void *cur, int64_t src_off, float amp,
                         const float *wavelet, int32_t *meta, hipStream_t s);
 hipError_t launch_get_field(int storage, const void *buf, float *out, int64_t nrows, int32_t nx,

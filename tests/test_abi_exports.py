@@ -58,6 +58,26 @@ def test_query_bytes_and_validation_on_host():
     assert e.value.status == _abi.FD_ERR_UNSUPPORTED
 
 
+def test_c_fixed16_sizes_and_validation_on_host():
+    import paper_2311_05038_amd as fd
+    from paper_2311_05038_amd import _abi
+    kw = dict(ndim=3, nz=512, ny=768, nx=768, dh=10.0, dt=1e-3, storage=fd.FD_BF16)
+    s32 = _abi.fd_query_bytes(fd.Grid(**kw).c())
+    s16 = _abi.fd_query_bytes(fd.Grid(c_storage=fd.FD_C_FIXED16, **kw).c())
+    cells = 512 * 768 * 768
+    assert s32.model - s16.model == cells * 2          # c: 4 -> 2 bytes per cell
+    assert s16.state == s32.state
+    # 16-bit c goes with 16-bit fields only; unknown kinds are rejected
+    with pytest.raises(fd.FDError) as e:
+        _abi.fd_query_bytes(fd.Grid(ndim=2, nz=10, ny=1, nx=10, dh=1.0, dt=1e-4,
+                                    c_storage=fd.FD_C_FIXED16).c())
+    assert e.value.status == _abi.FD_ERR_UNSUPPORTED
+    with pytest.raises(fd.FDError) as e:
+        _abi.fd_query_bytes(fd.Grid(ndim=2, nz=10, ny=1, nx=10, dh=1.0, dt=1e-4,
+                                    storage=fd.FD_F16, c_storage=3).c())
+    assert e.value.status == _abi.FD_ERR_INVALID_ARG
+
+
 def test_null_handles_are_rejected_on_host():
     from paper_2311_05038_amd import _abi
     lib = _abi.lib()

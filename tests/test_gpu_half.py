@@ -12,7 +12,9 @@ quantisation error itself.  The bars are therefore:
     of cells;
   * set/get round trip bit-exact against the oracle's encoder;
   * whole shots: the error against the FP64 oracle is stated and bounded,
-    and is of the same size as the emulation's own error."""
+    and is of the same size as the emulation's own error.
+Each is run with c in FP32 and with c in 16-bit fixed point (the emulation
+then quantises c the same way)."""
 import numpy as np
 import pytest
 import torch
@@ -49,16 +51,17 @@ def _ulp_of(x, storage, e):
     return 2.0 ** (ex - MANT[storage]) * 2.0 ** e
 
 
+@pytest.mark.parametrize("c16", [0, 1])
 @pytest.mark.parametrize("storage", [1, 2])
 @pytest.mark.parametrize("case", [0, 1, 2])
 @pytest.mark.parametrize("nsteps", [1, 3])
-def test_code_level_parity_from_identical_states(storage, case, nsteps):
+def test_code_level_parity_from_identical_states(storage, case, nsteps, c16):
     import paper_2311_05038_amd as fd
     p = _cases()[case]
-    print(f"case {p.name} storage={storage} nsteps={nsteps}", flush=True)
+    print(f"case {p.name} storage={storage} c16={c16} nsteps={nsteps}", flush=True)
     v, prev, cur = _start_state(p, 40)
     ps = p.scaled(nt=nsteps)
-    model, state, _ = setup(ps, v, storage=storage)
+    model, state, _ = setup(ps, v, storage=storage, c_storage=c16)
     wav = p.wavelet()[40:40 + nsteps].copy()
     shot = fd.Shot(p.src, torch.from_numpy(wav).cuda(), receivers_of(p))
     state.set_wavefield(0, torch.from_numpy(cur.ravel()).cuda())
@@ -68,7 +71,8 @@ def test_code_level_parity_from_identical_states(storage, case, nsteps):
         state.step(shot, n, tr[n])
     got = state.wavefield(0).cpu().numpy().reshape(-1)
     emu = oracle.forward_half(oracle.grid_of(ps), storage, v.reshape(p.nz, p.ny, p.nx), wav,
-                              nsteps, p.src, p.rec_index(), init_prev=prev, init_cur=cur)
+                              nsteps, p.src, p.rec_index(), init_prev=prev, init_cur=cur,
+                              c_fixed16=bool(c16))
     ref = emu["cur"].reshape(-1)
     diff = np.abs(got.astype(np.float64) - ref)
     amax = np.abs(ref).max()
@@ -102,16 +106,18 @@ def test_set_get_round_trip_matches_encoder(storage):
     np.testing.assert_array_equal(got.astype(np.float64), ref)
 
 
+@pytest.mark.parametrize("c16", [0, 1])
 @pytest.mark.parametrize("storage", [1, 2])
 @pytest.mark.parametrize("case", [0, 1, 2])
-def test_whole_shot_error_against_fp64_is_bounded(storage, case):
+def test_whole_shot_error_against_fp64_is_bounded(storage, case, c16):
     p = _cases()[case]
-    print(f"case {p.name} storage={storage}", flush=True)
+    print(f"case {p.name} storage={storage} c16={c16}", flush=True)
     v = p.velocity()
-    tr, cur = run(p, v, storage=storage)
+    tr, cur = run(p, v, storage=storage, c_storage=c16)
     g = oracle.grid_of(p)
     vv = v.reshape(p.nz, p.ny, p.nx)
-    emu = oracle.forward_half(g, storage, vv, p.wavelet(), p.nt, p.src, p.rec_index())
+    emu = oracle.forward_half(g, storage, vv, p.wavelet(), p.nt, p.src, p.rec_index(),
+                              c_fixed16=bool(c16))
     ref = oracle.forward(g, vv, p.wavelet(), p.nt, p.src, p.rec_index())
     e_gpu = max(rel_l2(tr, ref["traces"]), rel_l2(cur, ref["cur"].reshape(cur.shape)))
     e_emu = max(rel_l2(emu["traces"], ref["traces"]),

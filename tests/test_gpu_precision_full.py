@@ -15,8 +15,10 @@ their norm), the field norm, and the sampled final cells and 16^3 block sums:
         significand bits the stored fields lose the late-time field to
         accumulated quantisation error after 2000 steps; the traces, which
         record the early arrivals, keep 6% accuracy.
-The small whole-shot tests tie the 16-bit errors to the oracle's own 16-bit
-emulation (within 1.5x); at this size the emulation is out of reach."""
+The 16-bit forms also run with c in 16-bit fixed point (8 bytes per cell),
+under the same bounds.  The small whole-shot tests tie the 16-bit errors to
+the oracle's own 16-bit emulation (within 1.5x); at this size the emulation
+is out of reach."""
 import os
 
 import numpy as np
@@ -33,15 +35,15 @@ FIELD_BOUND = {0: 5e-4, 1: 5e-2, 2: 1.0}
 NAME = {0: "fp32", 1: "fp16", 2: "bf16"}
 
 
-@pytest.mark.parametrize("storage", [0, 1, 2])
-def test_precision3d_768_against_stored_oracle(storage):
+@pytest.mark.parametrize("storage,c16", [(0, 0), (1, 0), (2, 0), (1, 1), (2, 1)])
+def test_precision3d_768_against_stored_oracle(storage, c16):
     path = os.path.join(os.path.dirname(__file__), "golden", "precision3d_768.npz")
     if not os.path.exists(path):
         pytest.skip("stored oracle values not generated")
     gold = np.load(path)
     p = fi.precision3d()
-    print(f"precision3d 768x768x512 nt={p.nt} storage={NAME[storage]}", flush=True)
-    tr, cur = run(p, storage=storage)
+    print(f"precision3d 768x768x512 nt={p.nt} storage={NAME[storage]} c16={c16}", flush=True)
+    tr, cur = run(p, storage=storage, c_storage=c16)
     e_tr = rel_l2(tr[:, gold["traces_idx"]], gold["traces"])
     e_cells = rel_l2(cur.ravel()[gold["cells_idx"]], gold["cells"])
     b = 16
@@ -49,7 +51,7 @@ def test_precision3d_768_against_stored_oracle(storage):
     e_blocks = rel_l2(blocks, gold["blocks"])
     e_norm_f = abs(np.linalg.norm(cur.astype(np.float64)) / float(gold["field_norm"]) - 1)
     e_norm_t = abs(np.linalg.norm(tr.astype(np.float64)) / float(gold["trace_norm"]) - 1)
-    print(f"768x768x512 {NAME[storage]} errors vs FP64: traces {e_tr:.3e} cells {e_cells:.3e} "
+    print(f"768x768x512 {NAME[storage]}{'+c16' if c16 else ''} errors vs FP64: traces {e_tr:.3e} cells {e_cells:.3e} "
           f"blocks {e_blocks:.3e} field norm {e_norm_f:.3e} trace norm {e_norm_t:.3e}", flush=True)
     assert max(e_tr, e_norm_t) <= TRACE_BOUND[storage]
     assert e_norm_f <= NORM_BOUND[storage]

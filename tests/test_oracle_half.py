@@ -3,7 +3,11 @@
 The rounding of FP32 to binary16 and to bfloat16 is pinned bit-exactly
 against two library routines (numpy's float16 cast and torch's bfloat16 cast,
 both round-to-nearest-even); the FP32 arithmetic of the emulated time loop is
-pinned against the NumPy twin's independent emulation."""
+pinned against the NumPy twin's independent emulation.  The 16-bit
+fixed-point form of the model term c is pinned by its defining properties
+(scale bracket, nearest code with ties to even, cap, monotonicity), by the
+twin's separate implementation, and by models whose c values are codes
+already, for which it must change nothing."""
 import numpy as np
 import pytest
 import torch
@@ -79,3 +83,86 @@ def test_half_error_against_fp64_is_bounded(orc, storage, bound):
     assert e_tr <= bound and e_f <= bound, (e_tr, e_f)
     # 16-bit storage must cost more than FP32 rounding alone
     assert e_f > 1e-6
+
+
+def test_c_fixed16_codes_are_nearest_with_ties_to_even(orc):
+    rng = np.random.default_rng(21)
+    c = rng.uniform(0.01, 0.2, 50000).astype(np.float32)
+    c[0] = np.float32(0.2)                       # the largest value
+    q, e, dec = orc.c_fixed16(c)
+    M = float(c.max())
+    assert 2.0 ** (e - 1) <= M < 2.0 ** e        # the scale brackets the largest c
+    t = c.astype(np.float64) * 2.0 ** (16 - e)
+    qf = q.astype(np.float64)
+    assert np.all(np.abs(qf - t) <= 0.5)          # nearest code
+    assert np.all(np.abs(dec.astype(np.float64) - c) <= 2.0 ** (e - 17))
+    np.testing.assert_array_equal(dec.astype(np.float64), qf * 2.0 ** (e - 16))
+    order = np.argsort(c, kind="stable")
+    assert np.all(np.diff(qf[order]) >= 0)        # monotone
+    # exact midpoints between codes round to the even code
+    k = rng.integers(1000, 60000, 2000).astype(np.float64)
+    mid = np.concatenate([[M], (k + 0.5) * 2.0 ** (e - 16)]).astype(np.float32)
+    assert np.all(mid.astype(np.float64)[1:] == (k + 0.5) * 2.0 ** (e - 16))
+    qm, em, _ = orc.c_fixed16(mid)
+    assert em == e
+    assert np.all(qm[1:] % 2 == 0)
+    assert np.all(np.abs(qm[1:].astype(np.float64) - (k + 0.5)) == 0.5)
+
+
+def test_c_fixed16_cap_and_powers_of_two(orc):
+    # a largest c just below a power of two would round to 2^16: capped
+    top = np.nextafter(np.float32(0.25), np.float32(0.0))
+    q, e, dec = orc.c_fixed16(np.array([top, 0.125, 0.0625, 0.0], dtype=np.float32))
+    assert e == -2 and q[0] == 65535
+    assert q[1] == 32768 and q[2] == 16384 and q[3] == 0
+    # a largest c that is a power of two sits at the bottom of its bracket
+    q, e, _ = orc.c_fixed16(np.array([0.125, 0.03125], dtype=np.float32))
+    assert e == -2 and q[0] == 32768 and q[1] == 8192
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("ndim", [2, 3])
+def test_c_fixed16_emulation_matches_twin(orc, storage, ndim):
+    if ndim == 2:
+        p = fi.surface2d(26, 30, 70, seed=8).scaled(sponge_width=4, sponge_alpha=0.06)
+    else:
+        p = fi.layered3d(nx=14, ny=13, nz=12, nt=40)
+    v = fi.random_velocity(p.shape, 17)
+    shp = (p.nz, p.ny, p.nx)
+    out = orc.forward_half(orc.grid_of(p), storage, v.reshape(shp), p.wavelet(), p.nt, p.src,
+                           p.rec_index(), c_fixed16=True)
+    tr, cur = np_twin.Twin(p, v).forward_half(p.wavelet(), p.nt, storage, c_fixed16=True)
+    np.testing.assert_array_equal(out["traces"], tr)
+    np.testing.assert_array_equal(out["cur"].reshape(cur.shape), cur)
+    plain = orc.forward_half(orc.grid_of(p), storage, v.reshape(shp), p.wavelet(), p.nt, p.src,
+                             p.rec_index())
+    assert not np.array_equal(plain["cur"], out["cur"])   # the option takes effect
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+def test_c_fixed16_changes_nothing_when_c_is_a_code(orc, storage):
+    # dt/dh = 1e-4: v = 2500 gives c = 1/16, v = 1250 gives c = 1/64, both
+    # codes of the fixed-point grid (e = -3)
+    p = fi.surface2d(30, 34, 60, seed=8).scaled(dt=1e-3, dh=10.0)
+    v = np.full(p.shape, 2500.0, dtype=np.float32)
+    v[p.nz // 2:] = 1250.0
+    shp = (p.nz, 1, p.nx)
+    g = orc.grid_of(p)
+    a = orc.forward_half(g, storage, v.reshape(shp), p.wavelet(), p.nt, p.src, p.rec_index())
+    b = orc.forward_half(g, storage, v.reshape(shp), p.wavelet(), p.nt, p.src, p.rec_index(),
+                         c_fixed16=True)
+    np.testing.assert_array_equal(a["traces"], b["traces"])
+    np.testing.assert_array_equal(a["cur"], b["cur"])
+
+
+@pytest.mark.parametrize("storage,bound", [(1, 2e-3), (2, 3e-2)])
+def test_c_fixed16_error_against_fp64_is_bounded(orc, storage, bound):
+    p = fi.surface2d(48, 52, 150, seed=9)
+    v = fi.random_velocity(p.shape, 18, 2000, 3500)
+    shp = (p.nz, 1, p.nx)
+    g = orc.grid_of(p)
+    ref = orc.forward(g, v.reshape(shp), p.wavelet(), p.nt, p.src, p.rec_index())
+    out = orc.forward_half(g, storage, v.reshape(shp), p.wavelet(), p.nt, p.src, p.rec_index(),
+                           c_fixed16=True)
+    assert orc.rel_l2(out["traces"], ref["traces"]) <= bound
+    assert orc.rel_l2(out["cur"], ref["cur"]) <= bound
