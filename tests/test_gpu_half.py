@@ -125,3 +125,22 @@ def test_whole_shot_error_against_fp64_is_bounded(storage, case, c16):
     print(f"error vs fp64: gpu {e_gpu:.3e}  emulation {e_emu:.3e}", flush=True)
     assert e_gpu <= FP64_TOL[storage]
     assert e_gpu <= 1.5 * e_emu + 1e-4
+
+
+def test_c_fixed16_codes_match_oracle_bitwise():
+    # The set-up kernel's codes are integer results: equal to the oracle's
+    # quantiser on every cell.  The model buffer starts with c, padded to rows
+    # of 64 cells ([nz][ny][px], zero in the padding).
+    import paper_2311_05038_amd as fd
+    p = fi.layered3d(nx=70, ny=21, nz=19, nt=4)
+    v = fi.random_velocity(p.shape, 23, 1500, 4500)
+    model, _, _ = setup(p, v, storage=2, c_storage=fd.FD_C_FIXED16)
+    torch.cuda.synchronize()
+    px = (p.nx + 63) // 64 * 64
+    raw = model.buf[:p.nz * p.ny * px * 2].cpu().numpy().view(np.uint16).reshape(p.nz, p.ny, px)
+    r = p.dt / p.dh
+    c32 = ((v.astype(np.float64).reshape(p.nz, p.ny, p.nx) * r) ** 2).astype(np.float32)
+    q, e, _ = oracle.c_fixed16(c32)
+    np.testing.assert_array_equal(raw[:, :, :p.nx], q)
+    assert not raw[:, :, p.nx:].any()
+    assert q.max() > 32768          # the largest c sits in the top half of the code range
