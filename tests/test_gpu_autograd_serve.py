@@ -105,7 +105,9 @@ def test_shot_groups_equal_single_shot_calls():
     assert torch.equal(i3, i1)
 
 
-def test_serving_mix_equals_alone_bitwise():
+@pytest.mark.parametrize("policy,launch_cells", [("all", 1 << 24), ("srpt", 1 << 14)])
+def test_serving_mix_equals_alone_bitwise(policy, launch_cells):
+    # "srpt" with a small cell budget pauses and resumes shots between chunks
     import paper_2311_05038_amd as fd
     from paper_2311_05038_amd.serve import Request, Scheduler, TorchDevice
     reqs_in = fi.serving_stream(10, seed=7, rate=400.0, nz_range=(64, 200), nx_range=(64, 300),
@@ -119,7 +121,7 @@ def test_serving_mix_equals_alone_bitwise():
 
     reqs = [Request(r.rid, r.arrival, r.nz, r.nx, r.nt) for r in reqs_in]
     sch = Scheduler(TorchDevice(make_inputs, batched=True, keep_traces=True), max_slots=4,
-                    hbm_budget=1 << 34, chunk=7)
+                    hbm_budget=1 << 34, chunk=7, policy=policy, launch_cells=launch_cells)
     out = sch.run(reqs)
     assert sch.peak_slots <= 4
     for r in reqs:

@@ -133,3 +133,55 @@ def test_batching_beats_sequential_on_a_launch_bound_stream():
     assert bat["shots"] == seq["shots"] == 40
     assert bat["p99_latency_s"] < seq["p99_latency_s"]
     assert bat["shots_per_s"] > seq["shots_per_s"]
+
+
+class RecordingDevice(FakeDevice):
+    """FakeDevice that records which shots each chunk advanced."""
+
+    def __init__(self, **kw):
+        super().__init__(**kw)
+        self.calls = []
+
+    def advance(self, handles, nsteps):
+        self.calls.append([h["req"].rid for h in handles])
+        return super().advance(handles, nsteps)
+
+
+def test_srpt_policy_completes_every_shot_and_keeps_launches_full():
+    reqs = _stream(40)
+    dev = RecordingDevice()
+    cap = 4 << 20
+    out = Scheduler(dev, max_slots=64, hbm_budget=1 << 40, chunk=25, policy="srpt",
+                    launch_cells=cap, launch_max=16).run(reqs)
+    assert all(o.status == "ok" for o in out.values())
+    for r in reqs:
+        assert dev.steps[r.rid] == r.nt
+    size = {r.rid: r.nz * r.nx for r in reqs}
+    for call in dev.calls:
+        assert 1 <= len(call) <= 16
+        # shots are added until the launch holds `cap` cells: dropping the
+        # last one leaves it below the cap
+        assert sum(size[i] for i in call[:-1]) < cap
+
+
+def test_srpt_serves_short_shots_first():
+    # one long shot already running, then short ones: under "srpt" the short
+    # shots run alone (the long one waits), under "all" they share launches
+    reqs = [Request(0, 0.0, 2048, 2048, 4000)] + [Request(i, 0.01 + 0.001 * i, 512, 512, 1000)
+                                                  for i in range(1, 9)]
+    res = {}
+    for policy in ("all", "srpt"):
+        dev = RecordingDevice()
+        out = Scheduler(dev, max_slots=16, hbm_budget=1 << 40, chunk=25, policy=policy,
+                        launch_cells=1 << 20).run(reqs)
+        assert all(o.status == "ok" for o in out.values())
+        res[policy] = out
+    short_all = max(res["all"][i].latency for i in range(1, 9))
+    short_srpt = max(res["srpt"][i].latency for i in range(1, 9))
+    assert short_srpt < 0.7 * short_all
+    assert res["srpt"][0].latency >= res["all"][0].latency - 1e-9
+
+
+def test_unknown_policy_is_rejected():
+    with pytest.raises(ValueError):
+        Scheduler(FakeDevice(), policy="lifo")
