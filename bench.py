@@ -92,6 +92,32 @@ def copy_probe(nbytes: int = 1 << 30, reps: int = 20):
     return dict(bytes_per_copy=2 * nbytes, gbs=2 * nbytes * reps / (ms * 1e-3) / 1e9)
 
 
+def stream_probe(cells: int = 512 ** 3, reps: int = 20):
+    """The stencil step's traffic without the stencil: d = a + b * c
+    elementwise over three FP32 inputs and one output of the 512^3 size
+    (torch.addcmul: 12 B read + 4 B written per element), i.e. the practical
+    roof of a 3-read / 1-write stream on this GPU."""
+    import torch
+    a = torch.ones(cells, dtype=torch.float32, device="cuda")
+    b = torch.ones_like(a)
+    c = torch.ones_like(a)
+    d = torch.empty_like(a)
+    for _ in range(3):
+        torch.addcmul(a, b, c, out=d)
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record()
+    for _ in range(reps):
+        torch.addcmul(a, b, c, out=d)
+    t1.record()
+    torch.cuda.synchronize()
+    ms = t0.elapsed_time(t1) / reps
+    del a, b, c, d
+    torch.cuda.empty_cache()
+    return dict(us=ms * 1e3, gbs=16 * cells / (ms * 1e-3) / 1e9)
+
+
 def half_leg(nt: int = 2000):
     """16-bit storage vs FP32 on the 768x768x512 grid (same model, source,
     receivers): Mcell-updates/s of one whole shot each, with c in FP32
@@ -331,6 +357,8 @@ def main():
 
     probe = copy_probe()
     log(f"[bench] copy probe: {probe['gbs']:.0f} GB/s")
+    sprobe = stream_probe()
+    log(f"[bench] 3-read/1-write stream probe (512^3): {sprobe['us']:.1f} us, {sprobe['gbs']:.0f} GB/s")
     if args.probe_only:
         print(json.dumps({"copy_probe": probe}), flush=True)
         return
@@ -369,6 +397,7 @@ def main():
                      "bytes_per_cell": 16, "avg_launch_us": round(h["per_launch_us"], 2)},
         "cpu_baseline": cpu,
         "copy_roof_gbs": round(probe["gbs"], 1),
+        "stream_roof_gbs": round(sprobe["gbs"], 1),
     }
     out.update(extra)
     print(json.dumps(out), flush=True)
