@@ -631,7 +631,14 @@ fd_status backward_pass(const fd_model *model, const ShotIO *io, int32_t count, 
                 hist_mode);
             if (e != hipSuccess) return hip_fail(e, "recompute step");
         }
+        // Adjoint steps k = n1 .. n0+1, paired from the top of the segment:
+        // the first of a pair leaves its gradient term to the second, which
+        // adds both (z^(k+1) is its cur), so g is read and written once per
+        // two steps; an odd last step adds its own term.  The history of the
+        // segment is rebuilt by the next recompute, so pairs stay inside it.
         for (int64_t k = n1; k >= n0 + 1; --k) {
+            const int64_t j = n1 - k;
+            const int32_t gmode = (j & 1) ? 2 : (k - 1 >= n0 + 1 ? 1 : 0);
             hipError_t e = launch_all(
                 [&](int32_t i) {
                     StepArgs a = base_args(model, io[i].shot);
@@ -641,6 +648,8 @@ fd_status backward_pass(const fd_model *model, const ShotIO *io, int32_t count, 
                     a.n = k;
                     a.nt = 0;  // no source in the adjoint recursion
                     a.lap = hist(i, k - 1 - n0);
+                    a.lap2 = gmode == 2 ? hist(i, k - n0) : nullptr;
+                    a.gmode = gmode;
                     a.resid_row = nrec > 0 ? io[i].adj + (size_t)(k - 1) * (size_t)nrec : nullptr;
                     a.g = gsum(i);
                     return a;

@@ -77,9 +77,14 @@ struct StepArgs {
     RecBox rec;
     float *trace_row;     // nrec floats of row n, or null
     int32_t *meta;        // 16-bit storage: e[4] exponents then max|.|[4] bits
-    float *lap;           // kFwdLap/kFwdKeep: out (L cur / cur);  kAdj: in, padded FP32
+    float *lap;           // kFwdLap/kFwdKeep: out (L cur / cur);  kAdj: in (history of
+                          // level k-1), padded FP32
+    const float *lap2;    // kAdj, gmode 2: history of level k
     const float *resid_row;  // kAdj: dJ/dtraces row k-1 (nrec), or null
     double *g;            // kAdj: FP64 accumulator, padded
+    int32_t gmode;        // kAdj: 0 g += new hist; 1 no g update (deferred to the next
+                          // step); 2 g += cur lap2, then g += new lap (this step's
+                          // and the deferred term, in that order)
 };
 
 template <int ST> struct Stor { using T = uint16_t; };

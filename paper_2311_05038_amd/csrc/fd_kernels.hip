@@ -68,7 +68,9 @@ __device__ __forceinline__ void flush(Outgoing<T, VX> &out)
 // (16-bit fields: value = h.sn * nw).  FULL: every cell of the lane lies
 // inside the grid (x < nx), so no padding mask is needed.  The adjoint
 // step (which reads lap and g here) stores at once; the forward steps leave
-// their stores in `out`.
+// their stores in `out`.  lp: the history value to store (history modes), or
+// in the adjoint step the centre value of cur (the previous step's new
+// value, for a deferred gradient term).
 template <int ST, int VX, int MODE, bool STREAM, bool FULL>
 __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h, int z, int y,
                                              int x0, bool store_ok, size_t row, uint32_t eo,
@@ -136,9 +138,16 @@ __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h
     }
     if constexpr (MODE == kAdj) {
         flush<T, VX, MODE, STREAM>(out);
-        if (store_ok) {
+        // the time sum in FP64, one term per level in descending level order
+        // whether or not two terms share a pass over g
+        if (store_ok && a.gmode != 1) {
             const Pack<float, VX> lw = ldp<float, VX>(at(a.lap + row, eo));
             Pack<double, VX> gg = ldp<double, VX>(at(a.g + row, eo));
+            if (a.gmode == 2) {
+                const Pack<float, VX> lw2 = ldp<float, VX>(at(a.lap2 + row, eo));
+#pragma unroll
+                for (int v = 0; v < VX; ++v) gg.v[v] = fma((double)lp[v], (double)lw2.v[v], gg.v[v]);
+            }
 #pragma unroll
             for (int v = 0; v < VX; ++v) gg.v[v] = fma((double)nw[v], (double)lw.v[v], gg.v[v]);
             stp<double, VX>(at(a.g + row, eo), gg);
@@ -287,7 +296,7 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
             const float lap = fmaf(2.0f * kA0, q[4][v], lz + lx);
             G[v] = gzz * gxv[v];
             nw[v] = update<ST>(G[v], q[4][v], cc[v], lap, pc[v], h);
-            lp[v] = MODE == kFwdKeep ? q[4][v] : lap;
+            lp[v] = (MODE == kFwdKeep || MODE == kAdj) ? q[4][v] : lap;
         }
         finish_cells<ST, VX, MODE, false, false>(a, h, z, 0, x0, lane_in, (size_t)z * px, (uint32_t)x0, nw,
                                                  lp, cc, G, inj, bmax, out);
@@ -597,7 +606,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                     const float lap = fmaf(3.0f * kA0, q[j][4][v], lz + (lyv + lx));
                     G[v] = (gzz * gyv[j]) * gxv[v];
                     nw[v] = update<ST>(G[v], q[j][4][v], cc[j][v], lap, pc[j][v], h);
-                    lp[v] = MODE == kFwdKeep ? q[j][4][v] : lap;
+                    lp[v] = (MODE == kFwdKeep || MODE == kAdj) ? q[j][4][v] : lap;
                 }
                 }
                 if constexpr (OFF32)
