@@ -631,14 +631,18 @@ fd_status backward_pass(const fd_model *model, const ShotIO *io, int32_t count, 
                 hist_mode);
             if (e != hipSuccess) return hip_fail(e, "recompute step");
         }
-        // Adjoint steps k = n1 .. n0+1, paired from the top of the segment:
-        // the first of a pair leaves its gradient term to the second, which
-        // adds both (z^(k+1) is its cur), so g is read and written once per
-        // two steps; an odd last step adds its own term.  The history of the
-        // segment is rebuilt by the next recompute, so pairs stay inside it.
+        // Adjoint steps k = n1 .. n0+1 in groups of three from the top of the
+        // segment: the first two of a group leave their gradient terms to the
+        // last, which adds all three (z^(k+2) is its prev and z^(k+1) its cur,
+        // both read anyway), so g is read and written once per three steps.
+        // A shorter last group (two or one steps) works the same way.  The
+        // history of the segment is rebuilt by the next recompute, so groups
+        // stay inside it.
+        const int64_t m = n1 - n0;
         for (int64_t k = n1; k >= n0 + 1; --k) {
             const int64_t j = n1 - k;
-            const int32_t gmode = (j & 1) ? 2 : (k - 1 >= n0 + 1 ? 1 : 0);
+            const int64_t size = std::min<int64_t>(3, m - j / 3 * 3);
+            const int32_t gmode = j % 3 < size - 1 ? 1 : (size == 1 ? 0 : (int32_t)size);
             hipError_t e = launch_all(
                 [&](int32_t i) {
                     StepArgs a = base_args(model, io[i].shot);
@@ -648,7 +652,8 @@ fd_status backward_pass(const fd_model *model, const ShotIO *io, int32_t count, 
                     a.n = k;
                     a.nt = 0;  // no source in the adjoint recursion
                     a.lap = hist(i, k - 1 - n0);
-                    a.lap2 = gmode == 2 ? hist(i, k - n0) : nullptr;
+                    a.lap2 = gmode >= 2 ? hist(i, k - n0) : nullptr;
+                    a.lap3 = gmode == 3 ? hist(i, k + 1 - n0) : nullptr;
                     a.gmode = gmode;
                     a.resid_row = nrec > 0 ? io[i].adj + (size_t)(k - 1) * (size_t)nrec : nullptr;
                     a.g = gsum(i);

@@ -79,12 +79,14 @@ struct StepArgs {
     int32_t *meta;        // 16-bit storage: e[4] exponents then max|.|[4] bits
     float *lap;           // kFwdLap/kFwdKeep: out (L cur / cur);  kAdj: in (history of
                           // level k-1), padded FP32
-    const float *lap2;    // kAdj, gmode 2: history of level k
+    const float *lap2;    // kAdj, gmode 2 and 3: history of level k
+    const float *lap3;    // kAdj, gmode 3: history of level k+1
     const float *resid_row;  // kAdj: dJ/dtraces row k-1 (nrec), or null
     double *g;            // kAdj: FP64 accumulator, padded
-    int32_t gmode;        // kAdj: 0 g += new hist; 1 no g update (deferred to the next
-                          // step); 2 g += cur lap2, then g += new lap (this step's
-                          // and the deferred term, in that order)
+    int32_t gmode;        // kAdj: 0 g += new lap; 1 no g update (deferred to a later
+                          // step); 2 g += cur lap2, then new lap; 3 g += prev lap3,
+                          // then cur lap2, then new lap (the deferred terms first:
+                          // descending level order)
 };
 
 template <int ST> struct Stor { using T = uint16_t; };

@@ -70,12 +70,14 @@ __device__ __forceinline__ void flush(Outgoing<T, VX> &out)
 // step (which reads lap and g here) stores at once; the forward steps leave
 // their stores in `out`.  lp: the history value to store (history modes), or
 // in the adjoint step the centre value of cur (the previous step's new
-// value, for a deferred gradient term).
+// value, for a deferred gradient term); pv: the centre value of prev (the
+// new value of two steps back, for a second deferred term).
 template <int ST, int VX, int MODE, bool STREAM, bool FULL>
 __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h, int z, int y,
                                              int x0, bool store_ok, size_t row, uint32_t eo,
                                              float (&nw)[VX],
-                                             const float (&lp)[VX], const float (&cc)[VX],
+                                             const float (&lp)[VX], const float (&pv)[VX],
+                                             const float (&cc)[VX],
                                              const float (&G)[VX], float inj, float &bmax,
                                              Outgoing<typename Stor<ST>::T, VX> &out)
 {
@@ -139,11 +141,16 @@ __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h
     if constexpr (MODE == kAdj) {
         flush<T, VX, MODE, STREAM>(out);
         // the time sum in FP64, one term per level in descending level order
-        // whether or not two terms share a pass over g
+        // however many terms share a pass over g
         if (store_ok && a.gmode != 1) {
             const Pack<float, VX> lw = ldp<float, VX>(at(a.lap + row, eo));
             Pack<double, VX> gg = ldp<double, VX>(at(a.g + row, eo));
-            if (a.gmode == 2) {
+            if (a.gmode == 3) {
+                const Pack<float, VX> lw3 = ldp<float, VX>(at(a.lap3 + row, eo));
+#pragma unroll
+                for (int v = 0; v < VX; ++v) gg.v[v] = fma((double)pv[v], (double)lw3.v[v], gg.v[v]);
+            }
+            if (a.gmode >= 2) {
                 const Pack<float, VX> lw2 = ldp<float, VX>(at(a.lap2 + row, eo));
 #pragma unroll
                 for (int v = 0; v < VX; ++v) gg.v[v] = fma((double)lp[v], (double)lw2.v[v], gg.v[v]);
@@ -299,7 +306,7 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
             lp[v] = (MODE == kFwdKeep || MODE == kAdj) ? q[4][v] : lap;
         }
         finish_cells<ST, VX, MODE, false, false>(a, h, z, 0, x0, lane_in, (size_t)z * px, (uint32_t)x0, nw,
-                                                 lp, cc, G, inj, bmax, out);
+                                                 lp, pc, cc, G, inj, bmax, out);
         if constexpr (!LATE) flush<T, VX, MODE, false>(out);
 #pragma unroll
         for (int k = 0; k < 8; ++k)
@@ -611,12 +618,12 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                 }
                 if constexpr (OFF32)
                     finish_cells<ST, VX, MODE, true, FULL>(a, h, z, yj[j], x0, lane_in && yin[j],
-                                                           (size_t)z * pp, eo[j], nw, lp, cc[j], G, inj, bmax,
-                                                           out[j]);
+                                                           (size_t)z * pp, eo[j], nw, lp, pc[j], cc[j], G, inj,
+                                                           bmax, out[j]);
                 else
                     finish_cells<ST, VX, MODE, true, FULL>(a, h, z, yj[j], x0, lane_in && yin[j],
                                                            (size_t)z * pp + (size_t)yj[j] * px, (uint32_t)x0, nw,
-                                                           lp, cc[j], G, inj, bmax, out[j]);
+                                                           lp, pc[j], cc[j], G, inj, bmax, out[j]);
                 if constexpr (!LATE) flush<T, VX, MODE, true>(out[j]);
             }
         };
