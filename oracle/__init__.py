@@ -12,8 +12,10 @@ Parity status of each function (pins live in tests/test_oracle_*.py):
   laplacian     pinned: polynomial exactness, symmetry
   forward       pinned: 2D Green's function (with dt-halving convergence),
                 discrete energy conservation, reciprocity, NumPy twin
-  sponge        parity unpinned (no closed form); checked only through the
-                adjoint dot-product test and an absorption test
+  sponge        pinned: a uniform damping factor g maps the damped update
+                exactly onto the undamped one for P^n / g^n (forward_G);
+                profile properties (1 off the band, decreasing into it,
+                enabled faces only, G = product of the axis profiles)
   adjoint       pinned: dot-product test against the tangent-linear model and
                 central finite differences
   image         pinned: dot-product test against the NumPy twin's
@@ -79,6 +81,8 @@ def lib():
         L.or_adjoint.restype = ctypes.c_int
         L.or_image.argtypes = [P, P, P, i64, i64, i64, P, P, P]
         L.or_image.restype = ctypes.c_int
+        L.or_forward_G.argtypes = [P, P, P, P, i64, i64, i64, P, P, P, P, P, P]
+        L.or_forward_G.restype = ctypes.c_int
         L.or_forward_half.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, i64, i64, i64, P, P, P, P, P]
         L.or_c_fixed16.argtypes = [P, i64, P, P, ctypes.c_int]
         L.or_forward_half.restype = ctypes.c_int
@@ -159,6 +163,26 @@ def forward(grid: OrGrid, v: np.ndarray, wavelet: np.ndarray, nt: int, src, rec_
         out["lap"] = lap
     assert N == prev.size
     return out
+
+
+def forward_G(grid: OrGrid, v: np.ndarray, G: np.ndarray, nt: int, init_prev: np.ndarray,
+              init_cur: np.ndarray, rec_index=()):
+    """forward() from a given start state and no source, with the damping
+    field G (one value per cell) given instead of built from the band."""
+    v = np.ascontiguousarray(v, dtype=np.float32)
+    G = np.ascontiguousarray(G, dtype=np.float64)
+    ip = np.ascontiguousarray(init_prev, dtype=np.float64)
+    ic = np.ascontiguousarray(init_cur, dtype=np.float64)
+    rec = np.ascontiguousarray(rec_index, dtype=np.int64)
+    traces = np.zeros((nt, max(rec.size, 1)), dtype=np.float64)
+    prev = np.empty(v.shape, dtype=np.float64)
+    cur = np.empty(v.shape, dtype=np.float64)
+    wav = np.zeros(max(nt, 1), dtype=np.float32)
+    rc = lib().or_forward_G(ctypes.byref(grid), _p(v), _p(G), _p(wav), nt, -1, rec.size, _p(rec),
+                            _p(ip), _p(ic), _p(traces), _p(prev), _p(cur))
+    if rc != 0:
+        raise MemoryError("oracle forward_G: allocation failed")
+    return dict(traces=traces[:, :rec.size], prev=prev, cur=cur)
 
 
 def adjoint(grid: OrGrid, v: np.ndarray, wavelet: np.ndarray, nt: int, src, rec_index,

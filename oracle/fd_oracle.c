@@ -21,9 +21,11 @@
  *     derivatives, with no v^2 factor (Eq. 1 puts S outside v^2);
  *   - damping: new = G (2 cur + c L cur) - G^2 prev with G = product over
  *     axes of exp(-(alpha d)^2), d the distance into the band on enabled
- *     faces.  "parity unpinned": the sponge has no closed-form check; it is
- *     pinned only through the adjoint dot-product test and the absorption
- *     test.
+ *     faces.  How G enters the update is pinned by an exact identity (a
+ *     uniform G = g maps the scheme onto the undamped one for P^n / g^n);
+ *     the profile's shape is a reading, checked by its properties (1 off
+ *     the band, strictly decreasing into it, enabled faces only, G the
+ *     product of the axis profiles).
  *   - receivers sample the new field before the next source addition.
  *
  * Layout: arrays are row-major [nz][ny][nx], x fastest, ny = 1 in 2D.
@@ -166,20 +168,19 @@ static double source_amp(const or_grid *g)
  * lap_hist[n] = L(w^n) with w^n the field after step 1 of step n.
  * Returns 0, or -1 on allocation failure.
  */
-int or_forward(const or_grid *g, const float *v, const float *wavelet, int64_t nt,
-               int64_t src, int64_t nrec, const int64_t *rec,
-               const double *init_prev, const double *init_cur,
-               double *traces, double *final_prev, double *final_cur, double *lap_hist)
+/* The time loop of or_forward for given c and damping field G. */
+static int forward_loop(const or_grid *g, const double *c, const double *G, const float *wavelet,
+                        int64_t nt, int64_t src, int64_t nrec, const int64_t *rec,
+                        const double *init_prev, const double *init_cur, double *traces,
+                        double *final_prev, double *final_cur, double *lap_hist)
 {
     const int64_t N = g->nz * g->ny * g->nx;
-    double *c = malloc(sizeof(double) * N), *G = malloc(sizeof(double) * N);
     double *prev = calloc(N, sizeof(double)), *cur = calloc(N, sizeof(double));
     double *nw = malloc(sizeof(double) * N), *lap = malloc(sizeof(double) * N);
-    if (!c || !G || !prev || !cur || !nw || !lap) {
-        free(c); free(G); free(prev); free(cur); free(nw); free(lap);
+    if (!prev || !cur || !nw || !lap) {
+        free(prev); free(cur); free(nw); free(lap);
         return -1;
     }
-    or_setup(g, v, c, G);
     if (init_prev) memcpy(prev, init_prev, sizeof(double) * N);
     if (init_cur) memcpy(cur, init_cur, sizeof(double) * N);
     const double amp = source_amp(g);
@@ -199,8 +200,47 @@ int or_forward(const or_grid *g, const float *v, const float *wavelet, int64_t n
     }
     if (final_prev) memcpy(final_prev, prev, sizeof(double) * N);
     if (final_cur) memcpy(final_cur, cur, sizeof(double) * N);
-    free(c); free(G); free(prev); free(cur); free(nw); free(lap);
+    free(prev); free(cur); free(nw); free(lap);
     return 0;
+}
+
+int or_forward(const or_grid *g, const float *v, const float *wavelet, int64_t nt,
+               int64_t src, int64_t nrec, const int64_t *rec,
+               const double *init_prev, const double *init_cur,
+               double *traces, double *final_prev, double *final_cur, double *lap_hist)
+{
+    const int64_t N = g->nz * g->ny * g->nx;
+    double *c = malloc(sizeof(double) * N), *G = malloc(sizeof(double) * N);
+    if (!c || !G) {
+        free(c); free(G);
+        return -1;
+    }
+    or_setup(g, v, c, G);
+    int rc = forward_loop(g, c, G, wavelet, nt, src, nrec, rec, init_prev, init_cur, traces,
+                          final_prev, final_cur, lap_hist);
+    free(c); free(G);
+    return rc;
+}
+
+/* or_forward with a caller-given damping field G (N values) in place of the
+ * one built from the grid's band: the handle for pinning how the damping
+ * enters the update (a spatially uniform G = g turns the scheme into the
+ * undamped one for P^n / g^n). */
+int or_forward_G(const or_grid *g, const float *v, const double *G, const float *wavelet, int64_t nt,
+                 int64_t src, int64_t nrec, const int64_t *rec, const double *init_prev,
+                 const double *init_cur, double *traces, double *final_prev, double *final_cur)
+{
+    const int64_t N = g->nz * g->ny * g->nx;
+    double *c = malloc(sizeof(double) * N), *G0 = malloc(sizeof(double) * N);
+    if (!c || !G0) {
+        free(c); free(G0);
+        return -1;
+    }
+    or_setup(g, v, c, G0);
+    int rc = forward_loop(g, c, G, wavelet, nt, src, nrec, rec, init_prev, init_cur, traces,
+                          final_prev, final_cur, NULL);
+    free(c); free(G0);
+    return rc;
 }
 
 /*
