@@ -25,6 +25,9 @@ Parity status of each function (pins live in tests/test_oracle_*.py):
   forward_half  pinned: conversions bit-exact against numpy float16 and torch
                 bfloat16; the FP32 arithmetic against the NumPy twin's
                 emulation
+  c_fixed16     pinned: scale bracket, nearest code with ties to even, the
+                cap, monotonicity; the twin's separate implementation; models
+                whose c values are codes already run unchanged
 """
 from __future__ import annotations
 
