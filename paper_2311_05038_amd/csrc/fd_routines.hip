@@ -57,22 +57,38 @@ __global__ __launch_bounds__(256) void k_deriv_axis(const float *__restrict__ in
 }
 
 // Taps of the second difference along x: a thread owns 4 adjacent cells of
-// a row and reads the 12 values around them (neighbours' halo reads come
-// from the caches).  Cells past nx hold zeros in every field, and taps past
-// the padded row read zero.
+// a row and loads only those; the 4 values on each side come from the
+// neighbouring lanes through the wave (lanes hold consecutive groups of a
+// row), and only the wave's first and last lanes load them.  Cells past nx
+// hold zeros in every field, and taps past the padded row read zero.
 __global__ __launch_bounds__(256) void k_deriv_x(const float *__restrict__ in, float *__restrict__ out,
                                                  int64_t nrows, int32_t px)
 {
     const int32_t groups = px / 4;
     const int64_t w = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (w >= nrows * groups) return;
-    const int64_t row = w / groups;
-    const int32_t x0 = (int32_t)(w % groups) * 4;
+    const bool valid = w < nrows * groups;   // every lane takes part in the shuffles
+    const int64_t row = valid ? w / groups : 0;
+    const int32_t x0 = valid ? (int32_t)(w % groups) * 4 : 0;
+    const int lane = threadIdx.x & 63;
     const float *r = in + row * px;
     const float4 zero = make_float4(0.f, 0.f, 0.f, 0.f);
-    const float4 a = x0 >= 4 ? *reinterpret_cast<const float4 *>(r + x0 - 4) : zero;
-    const float4 b = *reinterpret_cast<const float4 *>(r + x0);
-    const float4 c = x0 + 4 < px ? *reinterpret_cast<const float4 *>(r + x0 + 4) : zero;
+    const float4 b = valid ? *reinterpret_cast<const float4 *>(r + x0) : zero;
+    float4 a, c;
+    a.x = __shfl_up(b.x, 1, 64);
+    a.y = __shfl_up(b.y, 1, 64);
+    a.z = __shfl_up(b.z, 1, 64);
+    a.w = __shfl_up(b.w, 1, 64);
+    c.x = __shfl_down(b.x, 1, 64);
+    c.y = __shfl_down(b.y, 1, 64);
+    c.z = __shfl_down(b.z, 1, 64);
+    c.w = __shfl_down(b.w, 1, 64);
+    if (!valid) return;
+    // the previous group is in this row when x0 >= 4, and in this wave
+    // unless this is its first lane (likewise for the next group)
+    if (x0 < 4) a = zero;
+    else if (lane == 0) a = *reinterpret_cast<const float4 *>(r + x0 - 4);
+    if (x0 + 4 >= px) c = zero;
+    else if (lane == 63) c = *reinterpret_cast<const float4 *>(r + x0 + 4);
     const float u[12] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w, c.x, c.y, c.z, c.w};
     float o[4];
 #pragma unroll
