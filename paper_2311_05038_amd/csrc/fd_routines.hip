@@ -20,6 +20,7 @@ namespace {
 // chunk of it with a 9-deep register queue, so each input value is read
 // once.  Work item w = (outer line, chunk, x group), x group fastest, so the
 // chunks that share halo planes run close together.
+template <bool STREAM>
 __global__ __launch_bounds__(256) void k_deriv_axis(const float *__restrict__ in,
                                                     float *__restrict__ out, int32_t n_axis,
                                                     int64_t axis_stride, int32_t n_outer,
@@ -50,7 +51,10 @@ __global__ __launch_bounds__(256) void k_deriv_axis(const float *__restrict__ in
         r.y = stencil_taps(q[0].y, q[1].y, q[2].y, q[3].y, q[5].y, q[6].y, q[7].y, q[8].y);
         r.z = stencil_taps(q[0].z, q[1].z, q[2].z, q[3].z, q[5].z, q[6].z, q[7].z, q[8].z);
         r.w = stencil_taps(q[0].w, q[1].w, q[2].w, q[3].w, q[5].w, q[6].w, q[7].w, q[8].w);
-        *reinterpret_cast<float4 *>(obase + (int64_t)k * axis_stride) = r;
+        if constexpr (STREAM)
+            stp_stream<float, 4>(obase + (int64_t)k * axis_stride, Pack<float, 4>{{r.x, r.y, r.z, r.w}});
+        else
+            *reinterpret_cast<float4 *>(obase + (int64_t)k * axis_stride) = r;
 #pragma unroll
         for (int i = 0; i < 8; ++i) q[i] = q[i + 1];
     }
@@ -61,6 +65,7 @@ __global__ __launch_bounds__(256) void k_deriv_axis(const float *__restrict__ in
 // neighbouring lanes through the wave (lanes hold consecutive groups of a
 // row), and only the wave's first and last lanes load them.  Cells past nx
 // hold zeros in every field, and taps past the padded row read zero.
+template <bool STREAM>
 __global__ __launch_bounds__(256) void k_deriv_x(const float *__restrict__ in, float *__restrict__ out,
                                                  int64_t nrows, int32_t px)
 {
@@ -94,14 +99,22 @@ __global__ __launch_bounds__(256) void k_deriv_x(const float *__restrict__ in, f
 #pragma unroll
     for (int v = 0; v < 4; ++v)
         o[v] = stencil_taps(u[v], u[v + 1], u[v + 2], u[v + 3], u[v + 5], u[v + 6], u[v + 7], u[v + 8]);
-    *reinterpret_cast<float4 *>(out + row * px + x0) = make_float4(o[0], o[1], o[2], o[3]);
+    if constexpr (STREAM)
+        stp_stream<float, 4>(out + row * px + x0, Pack<float, 4>{{o[0], o[1], o[2], o[3]}});
+    else
+        *reinterpret_cast<float4 *>(out + row * px + x0) = make_float4(o[0], o[1], o[2], o[3]);
 }
 
 // Time update with the sponge, from the materialised derivative fields:
 //   L = a0 D cur + Pzz + (Pyy + Pxx)      (2D: a0 2 cur + Pzz + Pxx)
 //   new = G (2 cur + c L) - G^2 prev,  G = gz gy gx,
 // written over prev, with the receivers sampling `new`.
-template <int NDIM>
+// STREAM (all three kinds of routine kernels): non-temporal accesses, for
+// steps whose fields cannot stay in the Infinity Cache anyway (512^3: the
+// routine step 1,373 -> 1,229 us, fd_time 715 -> 591 us); on smaller grids
+// the cache keeps each kernel's output for the next kernel, and the ordinary
+// accesses are faster (2048x4096: fd_pzz 14.7 against 18.0 us).
+template <int NDIM, bool STREAM>
 __global__ __launch_bounds__(256) void k_time(StepArgs a, const float *__restrict__ dzz,
                                               const float *__restrict__ dxx,
                                               const float *__restrict__ dyy)
@@ -116,16 +129,19 @@ __global__ __launch_bounds__(256) void k_time(StepArgs a, const float *__restric
     const int64_t off = row * a.px + x0;
     const float *cur = (const float *)a.cur;
     float *prv = (float *)a.prev;
-    const float4 P = *reinterpret_cast<const float4 *>(cur + off);
-    const float4 Q = *reinterpret_cast<const float4 *>(prv + off);
-    const float4 C = *reinterpret_cast<const float4 *>(a.c + off);
-    const float4 Z = *reinterpret_cast<const float4 *>(dzz + off);
-    const float4 X = *reinterpret_cast<const float4 *>(dxx + off);
-    float4 Y = make_float4(0.f, 0.f, 0.f, 0.f);
-    if constexpr (NDIM == 3) Y = *reinterpret_cast<const float4 *>(dyy + off);
-    const float pv[4] = {P.x, P.y, P.z, P.w}, qv[4] = {Q.x, Q.y, Q.z, Q.w};
-    const float cv[4] = {C.x, C.y, C.z, C.w}, zv[4] = {Z.x, Z.y, Z.z, Z.w};
-    const float xv[4] = {X.x, X.y, X.z, X.w}, yv[4] = {Y.x, Y.y, Y.z, Y.w};
+    using P4 = Pack<float, 4>;
+    auto ld = [&](const float *p) -> P4 {
+        if constexpr (STREAM)
+            return ldp_stream<float, 4>(p);
+        else
+            return ldp<float, 4>(p);
+    };
+    const P4 P = ld(cur + off), Q = ld(prv + off), C = ld(a.c + off), Z = ld(dzz + off);
+    const P4 X = ld(dxx + off);
+    P4 Y{};
+    if constexpr (NDIM == 3) Y = ld(dyy + off);
+    const float(&pv)[4] = P.v, (&qv)[4] = Q.v, (&cv)[4] = C.v, (&zv)[4] = Z.v, (&xv)[4] = X.v,
+               (&yv)[4] = Y.v;
     const float gzz = a.gz[z];
     const float gzy = NDIM == 3 ? gzz * a.gy[y] : gzz;
     float nw[4];
@@ -153,7 +169,10 @@ __global__ __launch_bounds__(256) void k_time(StepArgs a, const float *__restric
             }
         }
     }
-    *reinterpret_cast<float4 *>(prv + off) = make_float4(nw[0], nw[1], nw[2], nw[3]);
+    if constexpr (STREAM)
+        stp_stream<float, 4>(prv + off, P4{{nw[0], nw[1], nw[2], nw[3]}});
+    else
+        stp<float, 4>(prv + off, P4{{nw[0], nw[1], nw[2], nw[3]}});
 }
 
 // The source addition of step n + 1 into the new field (none after the last
@@ -177,6 +196,9 @@ hipError_t launch_routines(const StepArgs &a, int ndim, float *dzz, float *dxx, 
     const int64_t nrows = (int64_t)a.nz * a.ny;
     const int64_t pp = (int64_t)a.ny * a.px;
     const float *cur = (const float *)a.cur;
+    // streaming accesses when the step's fields (ndim + 3 read by fd_time,
+    // one written) exceed the 256 MiB Infinity Cache
+    const bool stream = (double)nrows * (double)a.px * 4.0 * (ndim + 4) > 256.0 * 1048576.0;
     // chunk of an axis walk: the longest (<= 64) that still gives >= 2^19
     // threads, at least 8
     auto chunk_for = [&](int64_t n_axis, int64_t lines) {
@@ -188,26 +210,40 @@ hipError_t launch_routines(const StepArgs &a, int ndim, float *dzz, float *dxx, 
     {
         const int32_t ch = chunk_for(a.nz, (int64_t)a.ny * groups);
         const int64_t items = (int64_t)a.ny * groups * ((a.nz + ch - 1) / ch);
-        hipLaunchKernelGGL(k_deriv_axis, dim3(blocks_for(items, 256)), dim3(256), 0, s, cur, dzz,
-                           a.nz, pp, a.ny, (int64_t)a.px, a.px, ch);
+        if (stream)
+            hipLaunchKernelGGL(k_deriv_axis<true>, dim3(blocks_for(items, 256)), dim3(256), 0, s, cur, dzz,
+                               a.nz, pp, a.ny, (int64_t)a.px, a.px, ch);
+        else
+            hipLaunchKernelGGL(k_deriv_axis<false>, dim3(blocks_for(items, 256)), dim3(256), 0, s, cur, dzz,
+                               a.nz, pp, a.ny, (int64_t)a.px, a.px, ch);
     }
     // fd_pxx: along x, rows
-    hipLaunchKernelGGL(k_deriv_x, dim3(blocks_for(nrows * groups, 256)), dim3(256), 0, s, cur, dxx,
-                       nrows, a.px);
+    if (stream)
+        hipLaunchKernelGGL(k_deriv_x<true>, dim3(blocks_for(nrows * groups, 256)), dim3(256), 0, s, cur, dxx,
+                           nrows, a.px);
+    else
+        hipLaunchKernelGGL(k_deriv_x<false>, dim3(blocks_for(nrows * groups, 256)), dim3(256), 0, s, cur, dxx,
+                           nrows, a.px);
     // the y derivative of the 3D form: along y, lines over (z, x)
     if (ndim == 3) {
         const int32_t ch = chunk_for(a.ny, (int64_t)a.nz * groups);
         const int64_t items = (int64_t)a.nz * groups * ((a.ny + ch - 1) / ch);
-        hipLaunchKernelGGL(k_deriv_axis, dim3(blocks_for(items, 256)), dim3(256), 0, s, cur, dyy,
-                           a.ny, (int64_t)a.px, a.nz, pp, a.px, ch);
+        if (stream)
+            hipLaunchKernelGGL(k_deriv_axis<true>, dim3(blocks_for(items, 256)), dim3(256), 0, s, cur, dyy,
+                               a.ny, (int64_t)a.px, a.nz, pp, a.px, ch);
+        else
+            hipLaunchKernelGGL(k_deriv_axis<false>, dim3(blocks_for(items, 256)), dim3(256), 0, s, cur, dyy,
+                               a.ny, (int64_t)a.px, a.nz, pp, a.px, ch);
     }
     // fd_time
-    if (ndim == 3)
-        hipLaunchKernelGGL(k_time<3>, dim3(blocks_for(nrows * groups, 256)), dim3(256), 0, s, a, dzz,
-                           dxx, dyy);
-    else
-        hipLaunchKernelGGL(k_time<2>, dim3(blocks_for(nrows * groups, 256)), dim3(256), 0, s, a, dzz,
-                           dxx, dyy);
+    const dim3 tg(blocks_for(nrows * groups, 256)), tb(256);
+    if (ndim == 3) {
+        if (stream) hipLaunchKernelGGL((k_time<3, true>), tg, tb, 0, s, a, dzz, dxx, dyy);
+        else hipLaunchKernelGGL((k_time<3, false>), tg, tb, 0, s, a, dzz, dxx, dyy);
+    } else {
+        if (stream) hipLaunchKernelGGL((k_time<2, true>), tg, tb, 0, s, a, dzz, dxx, dyy);
+        else hipLaunchKernelGGL((k_time<2, false>), tg, tb, 0, s, a, dzz, dxx, dyy);
+    }
     // add_source
     hipLaunchKernelGGL(k_add_source, dim3(1), dim3(64), 0, s, a);
     return hipGetLastError();
