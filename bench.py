@@ -230,14 +230,15 @@ def serve_leg(n_requests: int = 60, seed: int = 50):
     reqs = [Request(r.rid, r.arrival, r.nz, r.nx, r.nt) for r in reqs_in]
     cells = {r.rid: r.nz * r.nx * r.nt for r in reqs}
     res = {}
-    # "batched": the shots with the least remaining work advance, enough of
-    # them to give each launch 16 M cells per step, the others wait resident;
-    # "batched_all": every admitted shot advances in every launch
+    # "batched": the earliest-arrived resident shot and then the shots with
+    # the least remaining work advance, enough of them to give each launch
+    # 16 M cells per step, the others wait resident; "batched_all": every
+    # admitted shot advances in every launch
     warm = [Request(i, 0.0, 512 + 256 * i, 1024, 200) for i in range(4)]
     Scheduler(TorchDevice(make_inputs, batched=True), hbm_budget=200 << 30).run(warm)
     Scheduler(TorchDevice(make_inputs, batched=False), max_slots=1, policy="all",
               hbm_budget=200 << 30).run(warm)
-    for name, batched, slots, policy in (("batched", True, 64, "srpt"),
+    for name, batched, slots, policy in (("batched", True, 64, "srpt_oldest"),
                                          ("batched_all", True, 16, "all"),
                                          ("sequential", False, 1, "all")):
         torch.cuda.synchronize()

@@ -105,7 +105,8 @@ def test_shot_groups_equal_single_shot_calls():
     assert torch.equal(i3, i1)
 
 
-@pytest.mark.parametrize("policy,launch_cells", [("all", 1 << 24), ("srpt", 1 << 14)])
+@pytest.mark.parametrize("policy,launch_cells", [("all", 1 << 24), ("srpt", 1 << 14),
+                                                 ("srpt_oldest", 1 << 14)])
 def test_serving_mix_equals_alone_bitwise(policy, launch_cells):
     # "srpt" with a small cell budget pauses and resumes shots between chunks
     import paper_2311_05038_amd as fd

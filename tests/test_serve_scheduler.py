@@ -185,3 +185,17 @@ def test_srpt_serves_short_shots_first():
 def test_unknown_policy_is_rejected():
     with pytest.raises(ValueError):
         Scheduler(FakeDevice(), policy="lifo")
+
+
+def test_srpt_oldest_always_advances_the_earliest_shot():
+    reqs = _stream(30)
+    dev = RecordingDevice()
+    out = Scheduler(dev, max_slots=64, hbm_budget=1 << 40, chunk=25, policy="srpt_oldest",
+                    launch_cells=1 << 20, launch_max=16).run(reqs)
+    assert all(o.status == "ok" for o in out.values())
+    for r in reqs:
+        assert dev.steps[r.rid] == r.nt
+    arrival = {r.rid: r.arrival for r in reqs}
+    # every chunk leads with the earliest-arrived shot still resident
+    for call in dev.calls:
+        assert call[0] == min(call, key=lambda i: arrival[i])
