@@ -315,15 +315,17 @@ def traffic_from_profiles(kernel_tag: str):
     return rec["bytes_per_launch"]
 
 
-def cpu_baseline(nsteps: int = 48):
-    """The FP64 oracle on the same 512^3 model for a few steps."""
+def cpu_baseline(nsteps: int = 48, threads: int = 0):
+    """The FP64 oracle on the same 512^3 model for a few steps, on all the
+    host cores this process may use (threads=0) or on the given count."""
     import oracle
     import fd_inputs as fi
     p = fi.layered3d(nt=nsteps)
     v = p.velocity()
     g = oracle.grid_of(p)
-    threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
-    os.environ["OMP_NUM_THREADS"] = str(threads)
+    if threads <= 0:
+        threads = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    threads = oracle.set_threads(threads)
     t = time.perf_counter()
     oracle.forward(g, v, p.wavelet(), p.nt, p.src, p.rec_index())
     dt = time.perf_counter() - t
@@ -374,7 +376,12 @@ def main():
         extra["serving"] = serve_leg(args.serve_requests)
     if "routines" in legs:
         extra["routines"] = routines_leg()
-    cpu = None if args.no_cpu else cpu_baseline()
+    cpu = cpu1 = None
+    if not args.no_cpu:
+        cpu = cpu_baseline()
+        log(f"[bench] oracle on {cpu['cores']} cores: {cpu['value']:.0f} Mcell-updates/s")
+        cpu1 = cpu_baseline(2, threads=1)
+        log(f"[bench] oracle on 1 core: {cpu1['value']:.1f} Mcell-updates/s")
     traffic = traffic_from_profiles("k_step3d_f32_layered3d_512")
     out = {
         "metric": "Mcell-updates/s",
@@ -397,6 +404,7 @@ def main():
                      "traffic": traffic, "kernel": "k_step3d<f32>",
                      "bytes_per_cell": 16, "avg_launch_us": round(h["per_launch_us"], 2)},
         "cpu_baseline": cpu,
+        "cpu_baseline_1core": cpu1,
         "copy_roof_gbs": round(probe["gbs"], 1),
         "stream_roof_gbs": round(sprobe["gbs"], 1),
     }

@@ -84,6 +84,8 @@ def lib():
         L.or_adjoint.restype = ctypes.c_int
         L.or_image.argtypes = [P, P, P, i64, i64, i64, P, P, P]
         L.or_image.restype = ctypes.c_int
+        L.or_set_threads.argtypes = [ctypes.c_int]
+        L.or_set_threads.restype = ctypes.c_int
         L.or_forward_G.argtypes = [P, P, P, P, i64, i64, i64, P, P, P, P, P, P]
         L.or_forward_G.restype = ctypes.c_int
         L.or_forward_half.argtypes = [P, ctypes.c_int, ctypes.c_int, P, P, i64, i64, i64, P, P, P, P, P]
@@ -111,6 +113,12 @@ def coefficients(R: int) -> np.ndarray:
     a = np.zeros(9, dtype=np.float64)
     lib().or_coefficients(R, _p(a))
     return a[: R + 1].copy()
+
+
+def set_threads(n: int) -> int:
+    """Threads of the oracle's parallel loops from now on; returns the count
+    in effect."""
+    return int(lib().or_set_threads(int(n)))
 
 
 def sponge_profile(n: int, width: int, alpha: float, lo: bool, hi: bool) -> np.ndarray:
