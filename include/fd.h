@@ -55,7 +55,7 @@ typedef enum {
     FD_ERR_UNSTABLE = 2,      /* velocity/time step violate the stability bound */
     FD_ERR_OUT_OF_MEMORY = 3, /* host allocation of a handle failed */
     FD_ERR_DEVICE = 4,        /* a HIP call or kernel launch failed */
-    FD_ERR_UNSUPPORTED = 5    /* valid request this build does not implement */
+    FD_ERR_UNSUPPORTED = 5    /* valid request this library does not implement */
 } fd_status;
 
 typedef enum { FD_F32 = 0, FD_F16 = 1, FD_BF16 = 2 } fd_storage;
@@ -84,8 +84,8 @@ typedef enum { FD_BC_ZERO = 0, FD_BC_PERIODIC = 1 } fd_bc;
 /* The computational grid and its discretisation (Section 7: dh, dt). */
 typedef struct {
     int32_t ndim;          /* 2 or 3 */
-    int32_t radius;        /* stencil half-width; this build: 4 */
-    int32_t bc;            /* fd_bc; this build: FD_BC_ZERO */
+    int32_t radius;        /* stencil half-width; this library: 4 */
+    int32_t bc;            /* fd_bc; this library: FD_BC_ZERO */
     int32_t sponge_width;  /* cells in the damping band, 0 = none */
     int64_t nz, ny, nx;    /* cells; ny must be 1 when ndim == 2 */
     double dh;             /* grid spacing, m (> 0) */

@@ -6,7 +6,7 @@ hours for this run, so only samples are kept).
 
 Errors are stated (printed) and bounded, per storage, for the traces (and
 their norm), the field norm, and the sampled final cells and 16^3 block sums:
-  FP32: 1e-4 / 1e-4 / 5e-4.  The traces meet the benchmark spec's 1e-4 (7e-6), but
+  FP32: 1e-4 / 1e-4 / 5e-4.  The traces meet the 1e-4 bound (7e-6), but
         FP32 rounding of the leapfrog update keeps accumulating in the
         late-time field: after 2000 steps the sampled cells sit at 1.5e-4 and
         the block sums (a smooth, low-wavenumber view) at 2.5e-4.
