@@ -550,7 +550,7 @@ struct ShotIO {
 };
 
 fd_status backward_pass(const fd_model *model, const ShotIO *io, int32_t count, size_t ckpt_bytes,
-                        int32_t ckpt_every, size_t work_bytes, int hist_mode, hipStream_t s,
+                        int32_t ckpt_every, size_t work_bytes, bool image, hipStream_t s,
                         double **acc)
 {
     const Layout &L = model->L;
@@ -608,28 +608,56 @@ fd_status backward_pass(const fd_model *model, const ShotIO *io, int32_t count, 
         hipError_t e = fdk::launch_fill_u32(zf(i, 0), (2 * L.f32field + align_up(L.npad * 8)) / 4, 0u, s);
         if (e != hipSuccess) return hip_fail(e, "adjoint clear");
     }
+    auto ckpt_slot = [&](int32_t i, int64_t seg) -> char * {
+        return (char *)io[i].ckpt + (size_t)seg * ckpt_slot_bytes(L);
+    };
     for (int64_t seg = nseg - 1; seg >= 0; --seg) {
         const int64_t n0 = seg * ckpt_every;
         const int64_t n1 = std::min<int64_t>(nt, n0 + ckpt_every);
-        for (int32_t i = 0; i < count; ++i) {
-            const char *slot = (const char *)io[i].ckpt + (size_t)seg * ckpt_slot_bytes(L);
-            hipError_t e = hipMemcpyAsync(fw(i, n0), slot, L.field, hipMemcpyDeviceToDevice, s);
-            if (e == hipSuccess) e = hipMemcpyAsync(fw(i, n0 + 1), slot + L.field, L.field, hipMemcpyDeviceToDevice, s);
-            if (e != hipSuccess) return hip_fail(e, "checkpoint restore");
-        }
-        for (int64_t n = n0; n < n1; ++n) {
-            hipError_t e = launch_all(
-                [&](int32_t i) {
-                    StepArgs a = base_args(model, io[i].shot);
-                    a.cur = fw(i, n);
-                    a.prev = fw(i, n + 1);
-                    a.n = n;
-                    a.trace_row = nullptr;
-                    a.lap = hist(i, n - n0);
-                    return a;
-                },
-                hist_mode);
-            if (e != hipSuccess) return hip_fail(e, "recompute step");
+        if (image) {
+            // The image's history is the field itself: slot s holds w^(n0+s).
+            // Slot 0 is the checkpoint's P; each recompute step reads its
+            // Pold from the checkpoint or the slot before and writes the next
+            // level into the next slot (out of place), a plain forward step.
+            for (int32_t i = 0; i < count; ++i) {
+                hipError_t e = hipMemcpyAsync(hist(i, 0), ckpt_slot(i, seg), L.field, hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) return hip_fail(e, "checkpoint restore");
+            }
+            for (int64_t n = n0; n + 1 < n1; ++n) {
+                hipError_t e = launch_all(
+                    [&](int32_t i) {
+                        StepArgs a = base_args(model, io[i].shot);
+                        a.cur = hist(i, n - n0);
+                        a.prev = n == n0 ? (void *)(ckpt_slot(i, seg) + L.field) : (void *)hist(i, n - 1 - n0);
+                        a.out = hist(i, n + 1 - n0);
+                        a.n = n;
+                        a.trace_row = nullptr;
+                        return a;
+                    },
+                    fdk::kFwd);
+                if (e != hipSuccess) return hip_fail(e, "recompute step");
+            }
+        } else {
+            for (int32_t i = 0; i < count; ++i) {
+                const char *slot = ckpt_slot(i, seg);
+                hipError_t e = hipMemcpyAsync(fw(i, n0), slot, L.field, hipMemcpyDeviceToDevice, s);
+                if (e == hipSuccess) e = hipMemcpyAsync(fw(i, n0 + 1), slot + L.field, L.field, hipMemcpyDeviceToDevice, s);
+                if (e != hipSuccess) return hip_fail(e, "checkpoint restore");
+            }
+            for (int64_t n = n0; n < n1; ++n) {
+                hipError_t e = launch_all(
+                    [&](int32_t i) {
+                        StepArgs a = base_args(model, io[i].shot);
+                        a.cur = fw(i, n);
+                        a.prev = fw(i, n + 1);
+                        a.n = n;
+                        a.trace_row = nullptr;
+                        a.lap = hist(i, n - n0);
+                        return a;
+                    },
+                    fdk::kFwdLap);
+                if (e != hipSuccess) return hip_fail(e, "recompute step");
+            }
         }
         // Adjoint steps k = n1 .. n0+1 in groups of three from the top of the
         // segment: the first two of a group leave their gradient terms to the
@@ -703,7 +731,7 @@ fd_status backward_shots(const fd_model *model, const fd_shot *const *shots, int
     hipStream_t s = (hipStream_t)stream;
     std::vector<double *> acc((size_t)count, nullptr);
     fd_status st = backward_pass(model, io.data(), count, ckpt_bytes, ckpt_every, work_bytes,
-                                 image ? fdk::kFwdKeep : fdk::kFwdLap, s, acc.data());
+                                 image, s, acc.data());
     if (st != FD_OK) return st;
     const Layout &L = model->L;
     // shot after shot, so the FP64 sum has the order of one call per shot

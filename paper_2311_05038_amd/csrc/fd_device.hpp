@@ -38,13 +38,12 @@ __device__ __forceinline__ float leapfrog(float G, float ctr, float c, float lap
 
 enum Mode : int {
     kFwd = 0,     // forward step
-    kFwdLap = 1,  // forward step that also stores L(cur) (adjoint recompute)
-    kAdj = 2,     // adjoint step: receiver injection of c G r, g += new * hist
-    kFwdKeep = 3  // forward step that also stores cur itself (imaging recompute)
+    kFwdLap = 1,  // forward step that also stores L(cur) (gradient recompute)
+    kAdj = 2      // adjoint step: receiver injection of c G r, g += new * hist
 };
 
 // Forward modes that write a per-step history field (StepArgs::lap).
-constexpr bool stores_history(int mode) { return mode == kFwdLap || mode == kFwdKeep; }
+constexpr bool stores_history(int mode) { return mode == kFwdLap; }
 
 enum StorageKind : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
 
@@ -59,7 +58,8 @@ struct RecBox {
 // cells with x >= nx are zero in every field.
 struct StepArgs {
     const void *cur;      // level n
-    void *prev;           // level n-1 in, level n+1 out
+    void *prev;           // level n-1 in, level n+1 out (unless `out` is set)
+    void *out;            // forward steps: level n+1 here instead, prev only read
     const float *c;       // (v dt / h)^2, padded, zero in padding (FP32 c)
     const uint16_t *c16;  // or 16-bit fixed point: c = c16 * c16_scale (else null)
     float c16_scale;      // 2^(e - 16)
@@ -75,18 +75,19 @@ struct StepArgs {
     const float *wavelet; // device, nt samples
     int64_t n, nt;
     RecBox rec;
+    int32_t gmode;        // (fills the padding after rec)
+                          // kAdj: 0 g += new lap; 1 no g update (deferred to a later
+                          // step); 2 g += cur lap2, then new lap; 3 g += prev lap3,
+                          // then cur lap2, then new lap (the deferred terms first:
+                          // descending level order)
     float *trace_row;     // nrec floats of row n, or null
     int32_t *meta;        // 16-bit storage: e[4] exponents then max|.|[4] bits
-    float *lap;           // kFwdLap/kFwdKeep: out (L cur / cur);  kAdj: in (history of
-                          // level k-1), padded FP32
+    float *lap;           // kFwdLap: out (L cur);  kAdj: in (history of level k-1),
+                          // padded FP32
     const float *lap2;    // kAdj, gmode 2 and 3: history of level k
     const float *lap3;    // kAdj, gmode 3: history of level k+1
     const float *resid_row;  // kAdj: dJ/dtraces row k-1 (nrec), or null
     double *g;            // kAdj: FP64 accumulator, padded
-    int32_t gmode;        // kAdj: 0 g += new lap; 1 no g update (deferred to a later
-                          // step); 2 g += cur lap2, then new lap; 3 g += prev lap3,
-                          // then cur lap2, then new lap (the deferred terms first:
-                          // descending level order)
 };
 
 template <int ST> struct Stor { using T = uint16_t; };

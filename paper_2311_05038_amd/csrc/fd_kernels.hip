@@ -124,14 +124,14 @@ __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h
         if (!FULL && x0 + v >= a.nx) nw[v] = 0.0f;
         if constexpr (ST != kF32) bmax = fmaxf(bmax, fabsf(nw[v]));
     }
-    T *prv = (T *)a.prev;
+    T *dst = (T *)(a.out != nullptr ? a.out : a.prev);
     if constexpr (ST == kF32) {
 #pragma unroll
         for (int v = 0; v < VX; ++v) out.o.v[v] = nw[v];
     } else {
         encode_pairs<ST, VX>(nw, out.o.v);
     }
-    out.dst = at(prv + row, eo);
+    out.dst = at(dst + row, eo);
     out.ok = store_ok;
     if constexpr (stores_history(MODE)) {
 #pragma unroll
@@ -303,7 +303,7 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
             const float lap = fmaf(2.0f * kA0, q[4][v], lz + lx);
             G[v] = gzz * gxv[v];
             nw[v] = update<ST>(G[v], q[4][v], cc[v], lap, pc[v], h);
-            lp[v] = (MODE == kFwdKeep || MODE == kAdj) ? q[4][v] : lap;
+            lp[v] = MODE == kAdj ? q[4][v] : lap;
         }
         finish_cells<ST, VX, MODE, false, false>(a, h, z, 0, x0, lane_in, (size_t)z * px, (uint32_t)x0, nw,
                                                  lp, pc, cc, G, inj, bmax, out);
@@ -613,7 +613,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
                     const float lap = fmaf(3.0f * kA0, q[j][4][v], lz + (lyv + lx));
                     G[v] = (gzz * gyv[j]) * gxv[v];
                     nw[v] = update<ST>(G[v], q[j][4][v], cc[j][v], lap, pc[j][v], h);
-                    lp[v] = (MODE == kFwdKeep || MODE == kAdj) ? q[j][4][v] : lap;
+                    lp[v] = MODE == kAdj ? q[j][4][v] : lap;
                 }
                 }
                 if constexpr (OFF32)
@@ -1036,7 +1036,6 @@ static void launch2d(const StepArgs &a, int storage, int mode, int nb, hipStream
     if (storage == kF32) {
         if (mode == kFwd) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwd, false>), g, b, 0, s, a);
         else if (mode == kFwdLap) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwdLap, false>), g, b, 0, s, a);
-        else if (mode == kFwdKeep) hipLaunchKernelGGL((k_step2d<kF32, VX, kFwdKeep, false>), g, b, 0, s, a);
         else hipLaunchKernelGGL((k_step2d<kF32, VX, kAdj, false>), g, b, 0, s, a);
     } else if (storage == kF16) {
         if (cq) hipLaunchKernelGGL((k_step2d<kF16, VX, kFwd, true>), g, b, 0, s, a);
@@ -1060,7 +1059,6 @@ hipError_t launch_step(StepArgs a, int ndim, int storage, int mode, hipStream_t 
         if (storage == kF32) {
             if (mode == kFwd) launch3d<kF32, kFwd>(a, nb, s);
             else if (mode == kFwdLap) launch3d<kF32, kFwdLap>(a, nb, s);
-            else if (mode == kFwdKeep) launch3d<kF32, kFwdKeep>(a, nb, s);
             else launch3d<kF32, kAdj>(a, nb, s);
         } else if (storage == kF16) {
             if (a.c16 != nullptr) launch3d<kF16, kFwd, true>(a, nb, s);
@@ -1086,7 +1084,6 @@ hipError_t launch_step_batch2d(Batch2D &b, int mode, hipStream_t s)
     switch (mode) {
     case kFwd: hipLaunchKernelGGL((k_step2d_batch<kBatchVX, kFwd>), dim3(total), dim3(64), 0, s, b); break;
     case kFwdLap: hipLaunchKernelGGL((k_step2d_batch<kBatchVX, kFwdLap>), dim3(total), dim3(64), 0, s, b); break;
-    case kFwdKeep: hipLaunchKernelGGL((k_step2d_batch<kBatchVX, kFwdKeep>), dim3(total), dim3(64), 0, s, b); break;
     default: hipLaunchKernelGGL((k_step2d_batch<kBatchVX, kAdj>), dim3(total), dim3(64), 0, s, b); break;
     }
     return hipGetLastError();
