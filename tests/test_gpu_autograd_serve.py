@@ -133,3 +133,41 @@ def test_serving_mix_equals_alone_bitwise(policy, launch_cells):
         alone = m.run_shot(m.new_state(), shot)
         torch.cuda.synchronize()
         assert torch.equal(o.result, alone), r.rid
+
+
+def test_more_shots_than_one_launch_holds():
+    """18 shots in one multi-shot call (two launches per step: 16 + 2) give
+    every shot the bits of its own single-shot call: traces, checkpoints,
+    the gradient and the image summed shot after shot."""
+    import paper_2311_05038_amd as fd
+    ps = [fi.surface2d(24, 40, 40, seed=60, src_x=2 + 2 * i) for i in range(18)]
+    p = ps[0]
+    grid = grid_of(p)
+    v = torch.from_numpy(fi.random_velocity(p.shape, 61, 2000, 3000).ravel()).cuda()
+    m = fd.Model(grid, v)
+    shots = _shots(ps)
+    every = 7
+    states = [m.new_state() for _ in shots]
+    cks = [m.checkpoint_buffer(p.nt, every) for _ in shots]
+    tr = m.run_shots(states, shots, None, cks, every)
+    rng = np.random.default_rng(62)
+    adj = [torch.from_numpy(rng.standard_normal((p.nt, p.receivers.count)).astype(np.float32)).cuda()
+           for _ in shots]
+    g_all = torch.zeros(p.ncells, dtype=torch.float64, device="cuda")
+    m.adjoint_gradient_shots(shots, adj, cks, every, g_all)
+    i_all = torch.zeros(p.ncells, dtype=torch.float64, device="cuda")
+    m.rtm_image_shots(shots, adj, cks, every, i_all)
+    g_one = torch.zeros_like(g_all)
+    i_one = torch.zeros_like(i_all)
+    st = m.new_state()
+    for k, s in enumerate(shots):
+        ck = m.checkpoint_buffer(p.nt, every)
+        t = m.run_shot(st, s, ckpt=ck, ckpt_every=every)
+        torch.cuda.synchronize()
+        assert torch.equal(t, tr[k]), k
+        assert torch.equal(ck, cks[k]), k
+        m.adjoint_gradient(s, adj[k], ck, every, g_one)
+        m.rtm_image(s, adj[k], ck, every, i_one)
+    torch.cuda.synchronize()
+    assert torch.equal(g_all, g_one)
+    assert torch.equal(i_all, i_one)
