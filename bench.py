@@ -15,6 +15,9 @@ on the same GPU) add keys to the same line:
   adjoint  the 8-shot velocity gradient on the 1024^2 model, 2000 steps
   serve    a Poisson stream of 2D shots, continuous batching vs sequential
   routines the step as one kernel per routine vs the fused step
+  slab     one eighth of the headline grid as a z-slab with ghost planes (the
+           share of one device when the model is cut along z), with the
+           ghost exchange timed beside it
 """
 from __future__ import annotations
 
@@ -335,6 +338,71 @@ def cpu_baseline(nsteps: int = 48, threads: int = 0):
                        f"{dt:.1f} s")
 
 
+def slab_leg(nsteps: int = 200, ranks: int = 8):
+    """One rank's share of the 512^3 headline model cut along z into `ranks`
+    slabs: an interior slab (planes [192, 256), plus 4 ghost planes per side)
+    stepped alone with fd_step, from a random field, against 1/ranks of the
+    whole-grid step time measured here too.  Also times fd_slab_exchange
+    between two such slabs on this one device (2 x 4 planes of 1 MiB each way,
+    device-to-device copies; between devices this would be the point-to-point
+    link transfer, not measured here)."""
+    import numpy as np
+    import torch
+    import fd_inputs as fi
+    from helpers import grid_of, receivers_of, setup
+    import paper_2311_05038_amd as fd
+    p = fi.layered3d(nt=nsteps + 5)
+    v = p.velocity().reshape(p.nz, p.ny, p.nx)
+    per = p.nz // ranks
+    grids = grid_of(p).slabs([per] * ranks)
+    mid = ranks // 2 - 1
+    shot = fd.Shot(p.src, torch.from_numpy(p.wavelet()).cuda(), receivers_of(p))
+    gen = torch.Generator(device="cuda").manual_seed(5)
+
+    def slab_state(k):
+        z0 = grids[k].slab_z0
+        vt = torch.from_numpy(np.ascontiguousarray(v[z0:z0 + per]).reshape(-1)).cuda()
+        m = fd.Model(grids[k], vt)
+        st = m.new_state()
+        st.begin(shot)
+        for which in (1, 0):
+            st.set_wavefield(which, 1e-3 * torch.randn(grids[k].ncells, device="cuda", generator=gen))
+        return m, st
+
+    def timed(fn, n):
+        for i in range(5):
+            fn(i)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        e0.record()
+        for i in range(5, 5 + n):
+            fn(i)
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) * 1e3 / n
+
+    m, st = slab_state(mid)
+    m2, st2 = slab_state(mid + 1)
+    ex_us = timed(lambda n: fd.slab_exchange(st, st2), nsteps)   # both at step 0
+    del m2, st2
+    us = timed(lambda n: st.step(shot, n), nsteps)
+    wm, wst, _ = setup(p)
+    wst.begin(shot)
+    whole_us = timed(lambda n: wst.step(shot, n), nsteps)
+    cells = per * p.ny * p.nx
+    res = dict(grid=f"{per}x{p.ny}x{p.nx} (+2x4 ghost planes), planes [{grids[mid].slab_z0}, "
+                    f"{grids[mid].slab_z0 + per}) of {p.nz}",
+               us_per_step=round(us, 2), mcell_per_s=round(cells / (us * 1e-6) / 1e6, 1),
+               alg_gbs=round(16 * cells / (us * 1e-6) / 1e9, 1),
+               whole_grid_us_per_step=round(whole_us, 2),
+               whole_grid_share_us=round(whole_us / ranks, 2),
+               exchange_us_one_device=round(ex_us, 2))
+    log(f"[bench] slab leg: {res}")
+    del m, st, wm, wst
+    torch.cuda.empty_cache()
+    return res
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -343,13 +411,14 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--probe-only", action="store_true",
                     help="only the 1 GiB copy probe (counter calibration)")
-    ap.add_argument("--legs", default="half,adjoint,serve,routines",
-                    help="comma list of extra legs (half, adjoint, serve, routines) or 'none'")
+    ap.add_argument("--legs", default="half,adjoint,serve,routines,slab",
+                    help="comma list of extra legs (half, adjoint, serve, routines, slab) or 'none'")
     ap.add_argument("--serve-requests", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this engine runs on one GPU; --gpus {args.gpus} is not supported "
-              "(the multi-GPU z-slab decomposition is a design, not a build)", file=sys.stderr)
+              "(a z-slab steps one device's share; the exchange between devices is not built)",
+              file=sys.stderr)
         sys.exit(2)
     import torch
     if not torch.cuda.is_available():
@@ -376,6 +445,8 @@ def main():
         extra["serving"] = serve_leg(args.serve_requests)
     if "routines" in legs:
         extra["routines"] = routines_leg()
+    if "slab" in legs:
+        extra["slab"] = slab_leg()
     cpu = cpu1 = None
     if not args.no_cpu:
         cpu = cpu_baseline()

@@ -94,6 +94,30 @@ typedef struct {
     uint32_t sponge_faces; /* FD_FACE_* bits of the faces that damp */
     int32_t storage;       /* fd_storage of the wavefields (arithmetic is FP32) */
     int32_t c_storage;     /* fd_c_storage of c; FD_C_FIXED16 needs 16-bit fields */
+    /* z-slab of a larger grid: one share of a model cut along z (the slow
+     * axis) into consecutive slabs, each of which would sit on its own
+     * device.  slab_nz_global = 0 (the default) means an ordinary grid.
+     * Otherwise this grid is the planes [slab_z0, slab_z0 + nz) of a grid
+     * of slab_nz_global planes with the same ny, nx, dh, dt and sponge:
+     *  - the velocity given to fd_create_model covers the slab's nz planes;
+     *  - the damping band is placed in global z (the slab's planes get the
+     *    factors those planes have in the whole grid);
+     *  - each stored level carries 4 ghost planes on either side, which the
+     *    step reads (the stencil radius) and never writes; they are zero
+     *    after fd_begin_shot and are refilled from the neighbouring slabs by
+     *    fd_slab_exchange after fd_begin_shot and after every step (ghosts
+     *    beyond the global top and bottom stay zero: the grid's zero edges);
+     *  - shot coordinates (source, receivers) are global: a slab adds the
+     *    source only if it owns the source plane and writes only the trace
+     *    entries of the receivers in its own planes;
+     *  - fd_step, fd_begin_shot, fd_get_wavefield and fd_set_wavefield
+     *    (owned planes only) work on slabs; the whole-shot, adjoint, image,
+     *    batched and per-routine calls return FD_ERR_UNSUPPORTED.
+     * Slabs need ndim = 3, FP32 fields and FP32 c, and nz >= 4.  Stepping
+     * every slab of a grid with an exchange after each step gives the
+     * whole-grid fd_step results bit for bit. */
+    int64_t slab_z0;
+    int64_t slab_nz_global;
 } fd_grid;
 
 /* A regular receiver array: cells (z0 + i*dz, y0 + j*dy, x0 + k*dx) for
@@ -242,6 +266,19 @@ fd_status fd_get_wavefield(const fd_state *state, int32_t which, float *out, voi
  * rounded to nearest even.  On a state that has not begun a shot, the state
  * is first put at rest with next step 0.  No source addition is made. */
 fd_status fd_set_wavefield(fd_state *state, int32_t which, const float *in, void *stream);
+
+/* Refreshes the ghost planes between two neighbouring slabs of one grid
+ * (see fd_grid: `upper` owns the planes just above `lower`'s, i.e.
+ * upper's slab_z0 + nz == lower's slab_z0): the current level P's last 4
+ * owned planes of `upper` go into `lower`'s 4 leading ghost planes, and
+ * lower's first 4 owned planes into upper's 4 trailing ghost planes.  Both
+ * states must have begun the same shot and be at the same next step.  With
+ * one device per slab this is the per-step halo exchange between
+ * neighbouring devices; here both states are on the current device and the
+ * planes move by two device-to-device copies on `stream` (2 x 4 planes of
+ * ny * ceil(nx / 64) * 64 FP32 cells).  Stream-ordered; nothing else is
+ * changed. */
+fd_status fd_slab_exchange(const fd_state *upper, const fd_state *lower, void *stream);
 
 /* One batch entry for fd_step_batch: a shot in flight with its own model,
  * state and next step n; traces is device [nt][nrec] or NULL (row n is

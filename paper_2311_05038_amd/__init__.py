@@ -25,7 +25,7 @@ from ._abi import (FDError, FD_BF16, FD_C_F32, FD_C_FIXED16, FD_F16, FD_F32, FD_
                    fd_batch_item, fd_grid, fd_receivers, fd_shot, fd_sizes)
 
 __all__ = ["Grid", "Receivers", "Shot", "Model", "State", "FDError", "FD_F32", "FD_F16",
-           "FD_BF16", "FD_C_F32", "FD_C_FIXED16", "step_batch", "ensure_built"]
+           "FD_BF16", "FD_C_F32", "FD_C_FIXED16", "step_batch", "slab_exchange", "ensure_built"]
 
 FACES_NO_TOP = 0x3E
 
@@ -63,13 +63,30 @@ class Grid:
     c_storage: int = FD_C_F32
     radius: int = 4
     bc: int = 0
+    # z-slab [slab_z0, slab_z0 + nz) of a grid of slab_nz_global planes
+    # (0: an ordinary grid); see `slabs` and `slab_exchange`
+    slab_z0: int = 0
+    slab_nz_global: int = 0
 
     def c(self) -> fd_grid:
         return fd_grid(ndim=self.ndim, radius=self.radius, bc=self.bc,
                        sponge_width=self.sponge_width, nz=self.nz, ny=self.ny, nx=self.nx,
                        dh=self.dh, dt=self.dt, sponge_alpha=self.sponge_alpha,
                        sponge_faces=self.sponge_faces, storage=self.storage,
-                       c_storage=self.c_storage)
+                       c_storage=self.c_storage, slab_z0=self.slab_z0,
+                       slab_nz_global=self.slab_nz_global)
+
+    def slabs(self, counts: Sequence[int]) -> list:
+        """This grid cut along z into consecutive slabs of `counts` planes
+        (summing to nz), each a Grid of its own."""
+        if sum(counts) != self.nz:
+            raise ValueError(f"slab planes sum to {sum(counts)}, the grid has {self.nz}")
+        out, z0 = [], 0
+        for k in counts:
+            out.append(Grid(**{**self.__dict__, "nz": int(k), "slab_z0": z0,
+                               "slab_nz_global": self.nz}))
+            z0 += int(k)
+        return out
 
     @property
     def shape(self):
@@ -307,6 +324,12 @@ class State:
             except Exception:
                 pass
             self.handle = None
+
+
+def slab_exchange(upper: "State", lower: "State", stream=None) -> None:
+    """fd_slab_exchange: refresh the ghost planes between two neighbouring
+    z-slabs (upper's planes end where lower's begin)."""
+    _abi.fd_slab_exchange(upper.handle, lower.handle, _stream_handle(stream))
 
 
 def step_batch(entries: Sequence[tuple], nsteps: int, stream=None) -> list:

@@ -33,7 +33,8 @@ class fd_grid(ctypes.Structure):
                 ("sponge_width", ctypes.c_int32), ("nz", ctypes.c_int64), ("ny", ctypes.c_int64),
                 ("nx", ctypes.c_int64), ("dh", ctypes.c_double), ("dt", ctypes.c_double),
                 ("sponge_alpha", ctypes.c_double), ("sponge_faces", ctypes.c_uint32),
-                ("storage", ctypes.c_int32), ("c_storage", ctypes.c_int32)]
+                ("storage", ctypes.c_int32), ("c_storage", ctypes.c_int32),
+                ("slab_z0", ctypes.c_int64), ("slab_nz_global", ctypes.c_int64)]
 
 
 class fd_receivers(ctypes.Structure):
@@ -86,6 +87,7 @@ SIGNATURES = [
     ("fd_set_wavefield", ctypes.c_int, [_P, _I32, _P, _P]),
     ("fd_step_batch", ctypes.c_int, [ctypes.POINTER(fd_batch_item), _I32, _I32, _P]),
     ("fd_step_routines", ctypes.c_int, [_P, _P, ctypes.POINTER(fd_shot), _I64, _P, _P, _SZ, _P]),
+    ("fd_slab_exchange", ctypes.c_int, [_P, _P, _P]),
     ("fd_last_error", ctypes.c_char_p, []),
     ("fd_version", ctypes.c_char_p, []),
 ]
@@ -227,6 +229,10 @@ def fd_get_wavefield(state: int, which: int, out_ptr: int, stream: int) -> None:
 
 def fd_set_wavefield(state: int, which: int, in_ptr: int, stream: int) -> None:
     check(lib().fd_set_wavefield(state, which, in_ptr, stream))
+
+
+def fd_slab_exchange(upper: int, lower: int, stream: int) -> None:
+    check(lib().fd_slab_exchange(upper, lower, stream))
 
 
 def fd_step_batch(items, nsteps: int, stream: int) -> None:

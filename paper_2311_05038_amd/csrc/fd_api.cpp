@@ -2,6 +2,7 @@
 // management and kernel dispatch.  Declarations and semantics: include/fd.h.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -59,7 +60,16 @@ struct Layout {
     size_t cfield;     // bytes of the stored c (FP32 or 16-bit fixed point), aligned
     size_t c_off, gz_off, gy_off, gx_off, scratch_off, model_bytes;
     size_t state_bytes, meta_off;
+    // z-slab of a larger grid: global index of plane 0, global plane count
+    // (nz for an ordinary grid), and the bytes of the 4 ghost planes that
+    // precede (and follow) a slab's stored level (0 for an ordinary grid)
+    int64_t z0, nzg;
+    size_t ghost;
 };
+
+constexpr int kGhost = 4;  // the stencil radius
+
+bool is_slab(const Layout &L) { return L.nzg != L.nz || L.z0 != 0 || L.ghost != 0; }
 
 Layout make_layout(const fd_grid &g)
 {
@@ -73,7 +83,11 @@ Layout make_layout(const fd_grid &g)
     L.px = (int32_t)((g.nx + 63) / 64 * 64);
     L.npad = (size_t)g.nz * (size_t)g.ny * (size_t)L.px;
     L.elem = g.storage == FD_F32 ? 4 : 2;
-    L.field = align_up(L.npad * L.elem);
+    const bool slab = g.slab_nz_global > 0;
+    L.z0 = slab ? g.slab_z0 : 0;
+    L.nzg = slab ? g.slab_nz_global : g.nz;
+    L.ghost = slab ? (size_t)kGhost * (size_t)g.ny * (size_t)L.px * L.elem : 0;
+    L.field = align_up(L.npad * L.elem + 2 * L.ghost);
     L.f32field = align_up(L.npad * 4);
     L.cfield = g.c_storage == FD_C_FIXED16 ? align_up(L.npad * 2) : L.f32field;
     L.c_off = 0;
@@ -121,7 +135,21 @@ fd_status check_grid(const fd_grid *g)
         return fail(FD_ERR_INVALID_ARG, "unknown c storage kind %d", g->c_storage);
     if (g->c_storage == FD_C_FIXED16 && g->storage == FD_F32)
         return fail(FD_ERR_UNSUPPORTED, "16-bit c is built for 16-bit fields only");
-    const double cells = (double)g->nz * (double)g->ny * (double)((g->nx + 63) / 64 * 64);
+    if (g->slab_nz_global < 0 || g->slab_z0 < 0)
+        return fail(FD_ERR_INVALID_ARG, "slab_z0 and slab_nz_global must be >= 0");
+    if (g->slab_nz_global == 0 && g->slab_z0 != 0)
+        return fail(FD_ERR_INVALID_ARG, "slab_z0 needs slab_nz_global > 0");
+    if (g->slab_nz_global > 0) {
+        if (g->ndim != 3) return fail(FD_ERR_UNSUPPORTED, "z-slabs are built for 3D grids");
+        if (g->storage != FD_F32 || g->c_storage != FD_C_F32)
+            return fail(FD_ERR_UNSUPPORTED, "z-slabs are built for FP32 fields and FP32 c");
+        if (g->nz < kGhost) return fail(FD_ERR_INVALID_ARG, "a z-slab needs at least %d planes", kGhost);
+        if (g->slab_nz_global > kMaxDim || g->slab_z0 + g->nz > g->slab_nz_global)
+            return fail(FD_ERR_INVALID_ARG, "slab planes [%lld, %lld) leave the %lld-plane grid",
+                        (long long)g->slab_z0, (long long)(g->slab_z0 + g->nz),
+                        (long long)g->slab_nz_global);
+    }
+    const double cells = (double)(g->nz + 2 * kGhost) * (double)g->ny * (double)((g->nx + 63) / 64 * 64);
     if (cells > 4.0e9) return fail(FD_ERR_INVALID_ARG, "grid too large");
     // the 16-bit 3D kernels address a plane with 32-bit byte offsets
     if ((double)g->ny * (double)((g->nx + 63) / 64 * 64) >= 1073741824.0)
@@ -145,7 +173,8 @@ struct fd_model {
 
 struct fd_state {
     const fd_model *m;
-    void *buf[2];
+    void *base;    // the state buffer
+    void *buf[2];  // plane 0 of each stored level (past a slab's leading ghosts)
     int32_t *meta;
     int64_t next;  // next step index, -1 before fd_begin_shot
 };
@@ -158,7 +187,7 @@ fd_status check_shot(const fd_model *m, const fd_shot *s)
     const Layout &L = m->L;
     if (s->nt < 1) return fail(FD_ERR_INVALID_ARG, "shot nt must be >= 1");
     if (!s->wavelet) return fail(FD_ERR_INVALID_ARG, "shot wavelet is NULL");
-    if (s->src_z < 0 || s->src_z >= L.nz || s->src_y < 0 || s->src_y >= L.ny || s->src_x < 0 ||
+    if (s->src_z < 0 || s->src_z >= L.nzg || s->src_y < 0 || s->src_y >= L.ny || s->src_x < 0 ||
         s->src_x >= L.nx)
         return fail(FD_ERR_INVALID_ARG, "source cell (%lld, %lld, %lld) outside the grid",
                     (long long)s->src_z, (long long)s->src_y, (long long)s->src_x);
@@ -171,7 +200,7 @@ fd_status check_shot(const fd_model *m, const fd_shot *s)
     }
     if (nrec > ((int64_t)1 << 30)) return fail(FD_ERR_INVALID_ARG, "too many receivers");
     if (r.dz < 1 || r.dy < 1 || r.dx < 1) return fail(FD_ERR_INVALID_ARG, "receiver strides must be >= 1");
-    if (r.z0 < 0 || r.y0 < 0 || r.x0 < 0 || r.z0 + (r.nz - 1) * r.dz >= L.nz ||
+    if (r.z0 < 0 || r.y0 < 0 || r.x0 < 0 || r.z0 + (r.nz - 1) * r.dz >= L.nzg ||
         r.y0 + (r.ny - 1) * r.dy >= L.ny || r.x0 + (r.nx - 1) * r.dx >= L.nx)
         return fail(FD_ERR_INVALID_ARG, "receiver array leaves the grid");
     return FD_OK;
@@ -179,7 +208,11 @@ fd_status check_shot(const fd_model *m, const fd_shot *s)
 
 int64_t nrec_of(const fd_shot *s) { return s->rec.nz * s->rec.ny * s->rec.nx; }
 
-StepArgs base_args(const fd_model *m, const fd_shot *s)
+// Step arguments for a shot.  On a z-slab the global source plane and
+// receiver rows are made local: a source off the slab's planes gets plane
+// -1 (never matched), and only the receiver rows on the slab's planes stay,
+// *rec_skip being the entries of the full trace row that precede them.
+StepArgs base_args(const fd_model *m, const fd_shot *s, int64_t *rec_skip = nullptr)
 {
     StepArgs a{};
     const Layout &L = m->L;
@@ -196,18 +229,28 @@ StepArgs base_args(const fd_model *m, const fd_shot *s)
     a.px = L.px;
     a.amp = m->amp;
     if (s) {
-        a.sz = (int32_t)s->src_z;
+        const int64_t lz = s->src_z - L.z0;
+        a.sz = (lz >= 0 && lz < L.nz) ? (int32_t)lz : -1;
         a.sy = (int32_t)s->src_y;
         a.sx = (int32_t)s->src_x;
         a.wavelet = s->wavelet;
         a.nt = s->nt;
         const fd_receivers &r = s->rec;
-        if (nrec_of(s) > 0) {
-            a.rec = fdk::RecBox{(int32_t)r.z0, (int32_t)r.y0, (int32_t)r.x0, (int32_t)r.nz,
-                                (int32_t)r.ny, (int32_t)r.nx, (int32_t)r.dz, (int32_t)r.dy,
-                                (int32_t)r.dx};
+        // receiver rows i in [i0, i1) lie on planes [z0, z0 + nz)
+        int64_t i0 = 0, i1 = r.nz;
+        if (nrec_of(s) > 0 && is_slab(L)) {
+            i0 = std::max<int64_t>(0, (L.z0 - r.z0 + r.dz - 1) / r.dz);
+            const int64_t zl = L.z0 + L.nz - 1 - r.z0;  // the slab's last plane, from row 0
+            i1 = zl < 0 ? 0 : std::min<int64_t>(r.nz, zl / r.dz + 1);
+        }
+        if (nrec_of(s) > 0 && i1 > i0) {
+            a.rec = fdk::RecBox{(int32_t)(r.z0 + i0 * r.dz - L.z0), (int32_t)r.y0, (int32_t)r.x0,
+                                (int32_t)(i1 - i0), (int32_t)r.ny, (int32_t)r.nx, (int32_t)r.dz,
+                                (int32_t)r.dy, (int32_t)r.dx};
+            if (rec_skip) *rec_skip = i0 * r.ny * r.nx;
         } else {
             a.rec = fdk::RecBox{0, 0, 0, 0, 0, 0, 1, 1, 1};
+            if (rec_skip) *rec_skip = -1;
         }
     }
     return a;
@@ -221,11 +264,16 @@ size_t src_offset(const Layout &L, const fd_shot *s)
 fd_status do_begin(const fd_model *m, fd_state *st, const fd_shot *s, hipStream_t stream)
 {
     const Layout &L = m->L;
-    hipError_t e = fdk::launch_fill_u32(st->buf[0], L.state_bytes / 4, 0u, stream);
+    hipError_t e = fdk::launch_fill_u32(st->base, L.state_bytes / 4, 0u, stream);
     if (e != hipSuccess) return hip_fail(e, "fd_begin_shot fill");
-    e = fdk::launch_begin(L.storage, st->buf[0], (int64_t)src_offset(L, s), m->amp, s->wavelet,
-                          st->meta, stream);
-    if (e != hipSuccess) return hip_fail(e, "fd_begin_shot");
+    // a z-slab adds the source only on its own planes
+    if (s->src_z >= L.z0 && s->src_z < L.z0 + L.nz) {
+        fd_shot local = *s;
+        local.src_z -= L.z0;
+        e = fdk::launch_begin(L.storage, st->buf[0], (int64_t)src_offset(L, &local), m->amp,
+                              s->wavelet, st->meta, stream);
+        if (e != hipSuccess) return hip_fail(e, "fd_begin_shot");
+    }
     st->next = 0;
     return FD_OK;
 }
@@ -233,12 +281,14 @@ fd_status do_begin(const fd_model *m, fd_state *st, const fd_shot *s, hipStream_
 fd_status do_step(const fd_model *m, fd_state *st, const fd_shot *s, int64_t n, float *trace_row,
                   hipStream_t stream)
 {
-    StepArgs a = base_args(m, s);
+    int64_t skip = 0;
+    StepArgs a = base_args(m, s, &skip);
     a.cur = st->buf[n & 1];
     a.prev = st->buf[(n + 1) & 1];
     a.n = n;
-    a.trace_row = nrec_of(s) > 0 ? trace_row : nullptr;
+    a.trace_row = (nrec_of(s) > 0 && trace_row && skip >= 0) ? trace_row + skip : nullptr;
     a.meta = st->meta;
+    a.zghost = is_slab(m->L) ? (int16_t)kGhost : (int16_t)0;
     hipError_t e = fdk::launch_step(a, m->L.ndim, m->L.storage, fdk::kFwd, stream);
     if (e != hipSuccess) return hip_fail(e, "step kernel launch");
     st->next = n + 1;
@@ -262,9 +312,10 @@ fd_status fd_query_bytes(const fd_grid *grid, int64_t nt, int32_t ckpt_every, fd
     const Layout L = make_layout(*grid);
     out->model = L.model_bytes;
     out->state = L.state_bytes;
-    out->checkpoints = (nt > 0 && ckpt_every > 0) ? (size_t)n_ckpt(nt, ckpt_every) * ckpt_slot_bytes(L) : 0;
-    out->adjoint_work = ckpt_every > 0 ? adjoint_work_bytes(L, ckpt_every) : 0;
-    out->routines_work = (size_t)L.ndim * L.f32field;
+    const bool whole = !is_slab(L);  // slabs step one call at a time only
+    out->checkpoints = (whole && nt > 0 && ckpt_every > 0) ? (size_t)n_ckpt(nt, ckpt_every) * ckpt_slot_bytes(L) : 0;
+    out->adjoint_work = (whole && ckpt_every > 0) ? adjoint_work_bytes(L, ckpt_every) : 0;
+    out->routines_work = whole ? (size_t)L.ndim * L.f32field : 0;
     return ok();
 }
 
@@ -313,7 +364,9 @@ fd_status fd_create_model(const fd_grid *grid, const float *velocity, void *mode
         }
         return g;
     };
-    const std::vector<float> gz = profile(L.nz, f & FD_FACE_ZLO, f & FD_FACE_ZHI);
+    // a z-slab takes its planes' factors from the whole grid's profile
+    const std::vector<float> gzg = profile(L.nzg, f & FD_FACE_ZLO, f & FD_FACE_ZHI);
+    const std::vector<float> gz(gzg.begin() + L.z0, gzg.begin() + L.z0 + L.nz);
     const std::vector<float> gy = grid->ndim == 3 ? profile(L.ny, f & FD_FACE_YLO, f & FD_FACE_YHI)
                                                   : std::vector<float>(1, 1.0f);
     const std::vector<float> gx = profile(L.nx, f & FD_FACE_XLO, f & FD_FACE_XHI);
@@ -387,8 +440,9 @@ fd_status fd_create_state(const fd_model *model, void *state_buf, size_t state_b
     fd_state *st = new (std::nothrow) fd_state;
     if (!st) return fail(FD_ERR_OUT_OF_MEMORY, "host allocation failed");
     st->m = model;
-    st->buf[0] = state_buf;
-    st->buf[1] = (char *)state_buf + model->L.field;
+    st->base = state_buf;
+    st->buf[0] = (char *)state_buf + model->L.ghost;
+    st->buf[1] = (char *)state_buf + model->L.field + model->L.ghost;
     st->meta = (int32_t *)((char *)state_buf + model->L.meta_off);
     st->next = -1;
     *out = st;
@@ -435,6 +489,7 @@ fd_status fd_run_shot(const fd_model *model, fd_state *state, const fd_shot *sho
     fd_status st = check_shot(model, shot);
     if (st != FD_OK) return st;
     const Layout &L = model->L;
+    if (is_slab(L)) return fail(FD_ERR_UNSUPPORTED, "a z-slab steps with fd_step and fd_slab_exchange");
     if (ckpt) {
         if (ckpt_every < 1) return fail(FD_ERR_INVALID_ARG, "ckpt_every must be >= 1");
         const size_t need = (size_t)n_ckpt(shot->nt, ckpt_every) * ckpt_slot_bytes(L);
@@ -469,6 +524,7 @@ fd_status fd_run_shots(const fd_model *model, fd_state *const *states, const fd_
     if (count < 1 || count > 4096) return fail(FD_ERR_INVALID_ARG, "count must be in [1, 4096]");
     if (!states || !shots) return fail(FD_ERR_INVALID_ARG, "NULL states or shots array");
     const Layout &L = model->L;
+    if (is_slab(L)) return fail(FD_ERR_UNSUPPORTED, "a z-slab steps with fd_step and fd_slab_exchange");
     for (int32_t i = 0; i < count; ++i) {
         if (!states[i] || states[i]->m != model) return fail(FD_ERR_INVALID_ARG, "shot %d: state missing or of another model", i);
         fd_status st = check_shot(model, shots[i]);
@@ -726,6 +782,7 @@ fd_status backward_shots(const fd_model *model, const fd_shot *const *shots, int
     if (!out) return fail(FD_ERR_INVALID_ARG, image ? "NULL image" : "NULL grad_v");
     if (count < 1 || count > 4096) return fail(FD_ERR_INVALID_ARG, "count must be in [1, 4096]");
     if (!shots || !adj || !ckpt || !work) return fail(FD_ERR_INVALID_ARG, "NULL shots, adj, ckpt or work array");
+    if (is_slab(model->L)) return fail(FD_ERR_UNSUPPORTED, "the adjoint and the image are not built for z-slabs");
     std::vector<ShotIO> io((size_t)count);
     for (int32_t i = 0; i < count; ++i) io[i] = ShotIO{shots[i], adj[i], ckpt[i], work[i]};
     hipStream_t s = (hipStream_t)stream;
@@ -786,7 +843,7 @@ fd_status fd_set_wavefield(fd_state *state, int32_t which, const float *in, void
     const Layout &L = state->m->L;
     hipStream_t s = (hipStream_t)stream;
     if (state->next < 0) {
-        hipError_t e = fdk::launch_fill_u32(state->buf[0], L.state_bytes / 4, 0u, s);
+        hipError_t e = fdk::launch_fill_u32(state->base, L.state_bytes / 4, 0u, s);
         if (e != hipSuccess) return hip_fail(e, "fd_set_wavefield clear");
         state->next = 0;
     }
@@ -794,6 +851,34 @@ fd_status fd_set_wavefield(fd_state *state, int32_t which, const float *in, void
     hipError_t e = fdk::launch_set_field(L.storage, in, state->buf[lvl & 1], L.nz * L.ny,
                                          (int32_t)L.nx, L.px, state->meta, (int32_t)(lvl & 3), s);
     if (e != hipSuccess) return hip_fail(e, "fd_set_wavefield");
+    return ok();
+}
+
+fd_status fd_slab_exchange(const fd_state *upper, const fd_state *lower, void *stream)
+{
+    if (!upper || !lower) return fail(FD_ERR_INVALID_ARG, "NULL state");
+    if (upper == lower) return fail(FD_ERR_INVALID_ARG, "a slab cannot exchange with itself");
+    const Layout &U = upper->m->L, &D = lower->m->L;
+    if (!is_slab(U) || !is_slab(D)) return fail(FD_ERR_INVALID_ARG, "both states must be z-slabs");
+    if (U.nzg != D.nzg || U.ny != D.ny || U.nx != D.nx || U.storage != D.storage)
+        return fail(FD_ERR_INVALID_ARG, "the slabs belong to different grids");
+    if (U.z0 + U.nz != D.z0)
+        return fail(FD_ERR_INVALID_ARG, "upper's planes [%lld, %lld) do not end where lower's begin (%lld)",
+                    (long long)U.z0, (long long)(U.z0 + U.nz), (long long)D.z0);
+    if (upper->next < 0 || lower->next < 0) return fail(FD_ERR_INVALID_ARG, "fd_begin_shot has not been called");
+    if (upper->next != lower->next)
+        return fail(FD_ERR_INVALID_ARG, "the slabs are at different steps (%lld, %lld)",
+                    (long long)upper->next, (long long)lower->next);
+    const size_t plane = (size_t)U.ny * (size_t)U.px * U.elem;
+    const int64_t lvl = upper->next;  // P, the level the next step reads
+    const char *u = (const char *)upper->buf[lvl & 1];
+    const char *d = (const char *)lower->buf[lvl & 1];
+    hipStream_t s = (hipStream_t)stream;
+    hipError_t e = hipMemcpyAsync((char *)d - kGhost * plane, u + (size_t)(U.nz - kGhost) * plane,
+                                  kGhost * plane, hipMemcpyDeviceToDevice, s);
+    if (e == hipSuccess)
+        e = hipMemcpyAsync((char *)u + (size_t)U.nz * plane, d, kGhost * plane, hipMemcpyDeviceToDevice, s);
+    if (e != hipSuccess) return hip_fail(e, "fd_slab_exchange");
     return ok();
 }
 
@@ -806,6 +891,7 @@ fd_status fd_step_routines(const fd_model *model, fd_state *state, const fd_shot
     if (st != FD_OK) return st;
     const Layout &L = model->L;
     if (L.storage != FD_F32) return fail(FD_ERR_UNSUPPORTED, "the routine-per-kernel step is built for FP32 fields only");
+    if (is_slab(L)) return fail(FD_ERR_UNSUPPORTED, "the routine-per-kernel step is not built for z-slabs");
     if (!work) return fail(FD_ERR_INVALID_ARG, "work is NULL");
     if (work_bytes < (size_t)L.ndim * L.f32field)
         return fail(FD_ERR_INVALID_ARG, "work holds %zu bytes, %zu needed", work_bytes,
@@ -838,7 +924,7 @@ fd_status fd_step_batch(fd_batch_item *items, int32_t count, int32_t nsteps, voi
         const fd_batch_item &it = items[i];
         if (!it.model || !it.state) return fail(FD_ERR_INVALID_ARG, "item %d: NULL model or state", i);
         if (it.state->m != it.model) return fail(FD_ERR_INVALID_ARG, "item %d: state of another model", i);
-        if (it.model->L.ndim != 2 || it.model->L.storage != FD_F32)
+        if (it.model->L.ndim != 2 || it.model->L.storage != FD_F32 || is_slab(it.model->L))
             return fail(FD_ERR_UNSUPPORTED, "item %d: batching is built for 2D FP32 grids", i);
         fd_status st = check_shot(it.model, it.shot);
         if (st != FD_OK) return st;

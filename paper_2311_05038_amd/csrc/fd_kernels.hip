@@ -387,6 +387,7 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
     const int zb = tz * a.zc, ze = min(zb + a.zc, a.nz);
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const size_t px = (size_t)a.px, pp = (size_t)ny * px;
+    const int zlo = ST == kF32 ? -a.zghost : 0, zhi = ST == kF32 ? nz + a.zghost : nz;
     const bool lane_in = x0 < a.px;
     const T *__restrict__ cur = (const T *)a.cur;
     const T *__restrict__ prv = (const T *)a.prev;
@@ -468,9 +469,11 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
             cbase = a.c16;
         else
             cbase = a.c;
+        // cur (the only field read off its own planes) is readable over
+        // [-zghost, nz + zghost): a z-slab's ghost planes, or zero edges
         auto ld3 = [&](const T *base, int z, int j) -> PT {
             PT p{};
-            if (z >= 0 && z < nz && (FULL || (yin[j] && lane_in)))
+            if (z >= zlo && z < zhi && (FULL || (yin[j] && lane_in)))
                 p = ldp<T, VX>(addr(base, z, eo[j], yj[j], x0));
             return p;
         };

@@ -86,3 +86,31 @@ def test_null_handles_are_rejected_on_host():
     assert lib.fd_get_wavefield(None, 0, None, None) == _abi.FD_ERR_INVALID_ARG
     assert lib.fd_step_batch(None, 99, 1, None) == _abi.FD_ERR_INVALID_ARG
     assert b"count" in lib.fd_last_error()
+
+
+def test_z_slab_sizes_and_validation_on_host():
+    import paper_2311_05038_amd as fd
+    from paper_2311_05038_amd import _abi
+    whole = fd.Grid(ndim=3, nz=512, ny=512, nx=512, dh=10.0, dt=1e-3, sponge_width=32)
+    slabs = whole.slabs([64] * 8)
+    assert [(g.slab_z0, g.nz, g.slab_nz_global) for g in slabs][3] == (192, 64, 512)
+    s = _abi.fd_query_bytes(slabs[3].c(), 1000, 50)
+    plane = 512 * 512 * 4
+    # two levels of 64 owned + 2 x 4 ghost planes, and the 16-bit metadata words
+    assert 2 * 72 * plane <= s.state < 2 * 72 * plane + 4096
+    assert 64 * plane <= s.model < 64 * plane + 3 * 4096
+    assert s.checkpoints == 0 and s.adjoint_work == 0 and s.routines_work == 0
+    with pytest.raises(ValueError):
+        whole.slabs([64] * 7)
+    base = dict(ndim=3, nz=16, ny=8, nx=8, dh=1.0, dt=1e-4, slab_z0=0, slab_nz_global=40)
+    for kw, status in [(dict(ndim=2, ny=1), _abi.FD_ERR_UNSUPPORTED),
+                       (dict(storage=fd.FD_F16), _abi.FD_ERR_UNSUPPORTED),
+                       (dict(nz=3), _abi.FD_ERR_INVALID_ARG),
+                       (dict(slab_z0=30), _abi.FD_ERR_INVALID_ARG),
+                       (dict(slab_z0=-1), _abi.FD_ERR_INVALID_ARG),
+                       (dict(slab_nz_global=0, slab_z0=4), _abi.FD_ERR_INVALID_ARG)]:
+        with pytest.raises(fd.FDError) as e:
+            _abi.fd_query_bytes(fd.Grid(**{**base, **kw}).c())
+        assert e.value.status == status, kw
+    _abi.fd_query_bytes(fd.Grid(**{**base, "slab_z0": 24}).c())   # the last 16 planes
+    assert _abi.lib().fd_slab_exchange(None, None, None) == _abi.FD_ERR_INVALID_ARG
