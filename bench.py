@@ -351,7 +351,7 @@ def slab_leg(nsteps: int = 200, ranks: int = 8):
     import fd_inputs as fi
     from helpers import grid_of, receivers_of, setup
     import paper_2311_05038_amd as fd
-    p = fi.layered3d(nt=nsteps + 5)
+    p = fi.layered3d(nt=nsteps + 100)
     v = p.velocity().reshape(p.nz, p.ny, p.nx)
     per = p.nz // ranks
     grids = grid_of(p).slabs([per] * ranks)
@@ -369,13 +369,15 @@ def slab_leg(nsteps: int = 200, ranks: int = 8):
             st.set_wavefield(which, 1e-3 * torch.randn(grids[k].ncells, device="cuda", generator=gen))
         return m, st
 
-    def timed(fn, n):
-        for i in range(5):
+    def timed(fn, n, warm=100):
+        # a long warm-up: the first few hundred microseconds of a short
+        # kernel after host work measured up to 10% slow
+        for i in range(warm):
             fn(i)
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         torch.cuda.synchronize()
         e0.record()
-        for i in range(5, 5 + n):
+        for i in range(warm, warm + n):
             fn(i)
         e1.record()
         torch.cuda.synchronize()
