@@ -16,7 +16,7 @@ import torch
 
 import fd_inputs as fi
 import oracle
-from helpers import grid_of, receivers_of, rel_l2, run
+from helpers import grid_of, receivers_of, rel_l2
 
 pytestmark = pytest.mark.gpu
 TOL = 1e-4
@@ -119,4 +119,39 @@ def test_slab_call_errors():
     with pytest.raises(fd.FDError) as e:
         models[1].run_shot(states[1], shot)             # whole-shot calls: unsupported
     assert e.value.status == fd._abi.FD_ERR_UNSUPPORTED
+    torch.cuda.synchronize()
+
+
+def test_512_cube_in_8_slabs_equals_whole_grid():
+    """The headline grid (512^3, layered, 32-cell sponge, 256x256 receivers)
+    cut into the 8 slabs of 64 planes the bench times one of, 60 steps: the
+    whole traces and both levels, compared on the device, bit for bit."""
+    import paper_2311_05038_amd as fd
+    p = fi.layered3d(nt=60)
+    v = p.velocity()
+    print(f"case {p.name} nt={p.nt} slabs=8x64", flush=True)
+    models, states, shot = _slabs(p, v, [64] * 8)
+
+    def exchange():
+        for up, low in zip(states[:-1], states[1:]):
+            fd.slab_exchange(up, low)
+
+    for st in states:
+        st.begin(shot)
+    exchange()
+    tr = torch.full((p.nt, p.receivers.count), float("nan"), device="cuda")
+    for n in range(p.nt):
+        for st in states:
+            st.step(shot, n, tr[n])
+        exchange()
+    cur = torch.cat([st.wavefield(0) for st in states], 0)
+    old = torch.cat([st.wavefield(1) for st in states], 0)
+    del states, models
+    from helpers import setup
+    model, state, wshot = setup(p, v)
+    tw = model.run_shot(state, wshot)
+    assert torch.equal(tr, tw)
+    assert torch.equal(cur, state.wavefield(0))
+    assert torch.equal(old, state.wavefield(1))
+    assert float(cur.abs().max()) > 0
     torch.cuda.synchronize()
