@@ -105,8 +105,9 @@ typedef struct {
      *  - each stored level carries 4 ghost planes on either side, which the
      *    step reads (the stencil radius) and never writes; they are zero
      *    after fd_begin_shot and are refilled from the neighbouring slabs by
-     *    fd_slab_exchange after fd_begin_shot and after every step (ghosts
-     *    beyond the global top and bottom stay zero: the grid's zero edges);
+     *    fd_slab_exchange after fd_begin_shot, after fd_set_wavefield of P
+     *    and after every step (ghosts beyond the global top and bottom stay
+     *    zero: the grid's zero edges);
      *  - shot coordinates (source, receivers) are global: a slab adds the
      *    source only if it owns the source plane and writes only the trace
      *    entries of the receivers in its own planes;
