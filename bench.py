@@ -235,7 +235,7 @@ def serve_leg(n_requests: int = 60, seed: int = 50):
     res = {}
     # "batched": the earliest-arrived resident shot and then the shots with
     # the least remaining work advance, enough of them to give each launch
-    # 16 M cells per step, the others wait resident; "batched_all": every
+    # 12 M cells per step, the others wait resident; "batched_all": every
     # admitted shot advances in every launch
     warm = [Request(i, 0.0, 512 + 256 * i, 1024, 200) for i in range(4)]
     Scheduler(TorchDevice(make_inputs, batched=True), hbm_budget=200 << 30).run(warm)
@@ -246,7 +246,7 @@ def serve_leg(n_requests: int = 60, seed: int = 50):
                                          ("sequential", False, 1, "all")):
         torch.cuda.synchronize()
         sch = Scheduler(TorchDevice(make_inputs, batched=batched), max_slots=slots,
-                        hbm_budget=200 << 30, chunk=25, policy=policy, launch_cells=16 << 20)
+                        hbm_budget=200 << 30, chunk=25, policy=policy, launch_cells=12 << 20)
         out = sch.run(reqs)
         res[name] = {k: (round(v, 4) if isinstance(v, float) else v)
                      for k, v in summarize(out, cells.get).items()}
