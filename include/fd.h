@@ -152,8 +152,9 @@ typedef struct fd_model fd_model;
 typedef struct fd_state fd_state;
 
 /* Bytes of every caller-provided buffer for this grid.  nt and ckpt_every
- * only affect `checkpoints` and `adjoint_work` (pass 0 to skip them).
- * Host-only; no device work. */
+ * only affect `checkpoints` and `adjoint_work` (pass 0 to skip them).  For
+ * a z-slab, `state` includes the ghost planes and the buffers of the calls
+ * slabs do not support are 0.  Host-only; no device work. */
 fd_status fd_query_bytes(const fd_grid *grid, int64_t nt, int32_t ckpt_every, fd_sizes *out);
 
 /* Model setup (velocity V, dt, dh of Listing 3's WaveSimulator): computes
