@@ -342,10 +342,11 @@ def slab_leg(nsteps: int = 200, ranks: int = 8):
     """One rank's share of the 512^3 headline model cut along z into `ranks`
     slabs: an interior slab (planes [192, 256), plus 4 ghost planes per side)
     stepped alone with fd_step, from a random field, against 1/ranks of the
-    whole-grid step time measured here too.  Also times fd_slab_exchange
-    between two such slabs on this one device (2 x 4 planes of 1 MiB each way,
-    device-to-device copies; between devices this would be the point-to-point
-    link transfer, not measured here)."""
+    whole-grid step time measured here too; the same for 2, 4 and 16 slabs
+    (`shares`).  Also times fd_slab_exchange between two such slabs on this
+    one device (two device-to-device copies of 4 planes, 1 MiB per plane;
+    between devices this would be the point-to-point link transfer, not
+    measured here)."""
     import numpy as np
     import torch
     import fd_inputs as fi
@@ -353,21 +354,18 @@ def slab_leg(nsteps: int = 200, ranks: int = 8):
     import paper_2311_05038_amd as fd
     p = fi.layered3d(nt=nsteps + 100)
     v = p.velocity().reshape(p.nz, p.ny, p.nx)
-    per = p.nz // ranks
-    grids = grid_of(p).slabs([per] * ranks)
-    mid = ranks // 2 - 1
     shot = fd.Shot(p.src, torch.from_numpy(p.wavelet()).cuda(), receivers_of(p))
     gen = torch.Generator(device="cuda").manual_seed(5)
 
-    def slab_state(k):
-        z0 = grids[k].slab_z0
-        vt = torch.from_numpy(np.ascontiguousarray(v[z0:z0 + per]).reshape(-1)).cuda()
-        m = fd.Model(grids[k], vt)
+    def slab_state(nslabs, k):
+        g = grid_of(p).slabs([p.nz // nslabs] * nslabs)[k]
+        vt = torch.from_numpy(np.ascontiguousarray(v[g.slab_z0:g.slab_z0 + g.nz]).reshape(-1)).cuda()
+        m = fd.Model(g, vt)
         st = m.new_state()
         st.begin(shot)
         for which in (1, 0):
-            st.set_wavefield(which, 1e-3 * torch.randn(grids[k].ncells, device="cuda", generator=gen))
-        return m, st
+            st.set_wavefield(which, 1e-3 * torch.randn(g.ncells, device="cuda", generator=gen))
+        return g, m, st
 
     def timed(fn, n, warm=100):
         # a long warm-up: the first few hundred microseconds of a short
@@ -383,25 +381,39 @@ def slab_leg(nsteps: int = 200, ranks: int = 8):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) * 1e3 / n
 
-    m, st = slab_state(mid)
-    m2, st2 = slab_state(mid + 1)
-    ex_us = timed(lambda n: fd.slab_exchange(st, st2), nsteps)   # both at step 0
-    del m2, st2
-    us = timed(lambda n: st.step(shot, n), nsteps)
     wm, wst, _ = setup(p)
     wst.begin(shot)
     whole_us = timed(lambda n: wst.step(shot, n), nsteps)
-    cells = per * p.ny * p.nx
-    res = dict(grid=f"{per}x{p.ny}x{p.nx} (+2x4 ghost planes), planes [{grids[mid].slab_z0}, "
-                    f"{grids[mid].slab_z0 + per}) of {p.nz}",
+    del wm, wst
+    torch.cuda.empty_cache()
+    mid = ranks // 2 - 1
+    g, m, st = slab_state(ranks, mid)
+    _, m2, st2 = slab_state(ranks, mid + 1)
+    ex_us = timed(lambda n: fd.slab_exchange(st, st2), nsteps)   # both at step 0
+    del m2, st2
+    us = timed(lambda n: st.step(shot, n), nsteps)
+    del m, st
+    cells = g.ncells
+    shares = {}
+    for r in (2, 4, 8, 16):
+        if r == ranks:
+            u = us
+        else:
+            _, mr, sr = slab_state(r, r // 2 - 1)
+            u = timed(lambda n: sr.step(shot, n), nsteps)
+            del mr, sr
+        shares[str(r)] = dict(planes=p.nz // r, us_per_step=round(u, 2),
+                              share_us=round(whole_us / r, 2),
+                              efficiency=round(whole_us / r / u, 3))
+    torch.cuda.empty_cache()
+    res = dict(grid=f"{g.nz}x{p.ny}x{p.nx} (+2x4 ghost planes), planes [{g.slab_z0}, "
+                    f"{g.slab_z0 + g.nz}) of {p.nz}",
                us_per_step=round(us, 2), mcell_per_s=round(cells / (us * 1e-6) / 1e6, 1),
                alg_gbs=round(16 * cells / (us * 1e-6) / 1e9, 1),
                whole_grid_us_per_step=round(whole_us, 2),
                whole_grid_share_us=round(whole_us / ranks, 2),
-               exchange_us_one_device=round(ex_us, 2))
+               exchange_us_one_device=round(ex_us, 2), shares=shares)
     log(f"[bench] slab leg: {res}")
-    del m, st, wm, wst
-    torch.cuda.empty_cache()
     return res
 
 
