@@ -83,6 +83,16 @@ def test_3d_tile_multiples_and_deep_chunks():
     _check(p)
 
 
+def test_3d_short_column_in_short_chunks():
+    # 18 planes under 18 column tiles: the plan cuts each column into chunks
+    # of 5, 5, 5 and a ragged 3 (chunks down to 4 planes keep short columns
+    # filling the device)
+    p = fi.Problem(name="short3d", ndim=3, nz=18, ny=70, nx=300, dh=10.0, dt=1e-3, nt=40,
+                   src=(9, 35, 150), receivers=fi.Receivers(1, 2, 3, 4, 7, 30, 5, 10, 10),
+                   f0=25.0, sponge_width=3, sponge_faces=fi.FACES_ALL)
+    _check(p, fi.random_velocity(p.shape, 6, 1500, 3500))
+
+
 def test_single_cell_grids():
     for ndim in (2, 3):
         p = fi.Problem(name=f"one{ndim}", ndim=ndim, nz=1, ny=1, nx=1, dh=10.0, dt=1e-3, nt=20,
