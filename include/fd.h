@@ -61,12 +61,13 @@ typedef enum {
 typedef enum { FD_F32 = 0, FD_F16 = 1, FD_BF16 = 2 } fd_storage;
 /* Storage of the model term c = (v dt / dh)^2.  FD_C_FIXED16 (with 16-bit
  * fields only) keeps c as unsigned 16-bit fixed point with one power-of-two
- * scale, q = min(RNE(c 2^(16-e)), 65535) with e = floor(log2 max c) + 1, so
- * the step reads 8 bytes per cell instead of 10; |c - q 2^(e-16)| is at
- * most 2^(e-17) (c is first rounded to FP32 from the FP64 product), a
- * relative error of at most (max c / c) 2^-17 in c: 6.9e-5 for a 3:1
- * velocity contrast, 7.6e-4 for 10:1.  Models with far larger contrasts
- * should keep FD_C_F32. */
+ * scale, q = RNE(c 2^(16-e)) with e = floor(log2 max c) + 1, raised by one
+ * when max c lies within half a code of 2^e (so that every code fits 16
+ * bits), so the step reads 8 bytes per cell instead of 10; |c - q 2^(e-16)|
+ * is at most 2^(e-17) for every cell (c is first rounded to FP32 from the
+ * FP64 product), a relative error of at most (max c / c) 2^-17 in c
+ * (2^-16 in the raised case): 6.9e-5 for a 3:1 velocity contrast, 7.6e-4
+ * for 10:1.  Models with far larger contrasts should keep FD_C_F32. */
 typedef enum { FD_C_F32 = 0, FD_C_FIXED16 = 1 } fd_c_storage;
 typedef enum { FD_BC_ZERO = 0, FD_BC_PERIODIC = 1 } fd_bc;
 
@@ -151,10 +152,16 @@ typedef struct {
 typedef struct fd_model fd_model;
 typedef struct fd_state fd_state;
 
-/* Bytes of every caller-provided buffer for this grid.  nt and ckpt_every
- * only affect `checkpoints` and `adjoint_work` (pass 0 to skip them).  For
- * a z-slab, `state` includes the ghost planes and the buffers of the calls
- * slabs do not support are 0.  Host-only; no device work. */
+/* Bytes of every caller-provided buffer for this grid (Section 5, Start and
+ * stop: the containers the algorithms work on live in the device memory
+ * space and are filled from, and emptied to, the host by explicit copies;
+ * here the caller allocates that device memory, so it needs the sizes).
+ * nt and ckpt_every only affect `checkpoints` and `adjoint_work` (pass 0 to
+ * skip them).  For a z-slab, `state` includes the ghost planes and the
+ * buffers of the calls slabs do not support are 0.  Host-only; no device
+ * work.  Errors: FD_ERR_INVALID_ARG for a NULL grid or out, an invalid grid
+ * or negative nt / ckpt_every; FD_ERR_UNSUPPORTED for a valid grid this
+ * library does not build (*out is then untouched). */
 fd_status fd_query_bytes(const fd_grid *grid, int64_t nt, int32_t ckpt_every, fd_sizes *out);
 
 /* Model setup (velocity V, dt, dh of Listing 3's WaveSimulator): computes
@@ -169,8 +176,14 @@ fd_status fd_create_model(const fd_grid *grid, const float *velocity, void *mode
                           size_t model_bytes, void *stream, fd_model **out);
 fd_status fd_destroy_model(fd_model *model);
 
-/* Binds a state (the two time levels P and Pold) to `state_buf` (device,
- * >= fd_sizes.state bytes).  Host-only; call fd_begin_shot before stepping. */
+/* Binds a state (the two time levels P and Pold of Listing 3's
+ * WaveSimulator, Section 7) to `state_buf` (device, >= fd_sizes.state
+ * bytes, 256-byte aligned, owned by the caller and borrowed until
+ * fd_destroy_state): the device-resident container of Section 5 (Start and
+ * stop).  Host-only; call fd_begin_shot (or fd_set_wavefield) before
+ * stepping.  Errors: FD_ERR_INVALID_ARG for NULL arguments, a short or
+ * misaligned buffer; FD_ERR_OUT_OF_MEMORY if the host handle cannot be
+ * allocated. */
 fd_status fd_create_state(const fd_model *model, void *state_buf, size_t state_bytes,
                           fd_state **out);
 fd_status fd_destroy_state(fd_state *state);
@@ -188,11 +201,15 @@ fd_status fd_begin_shot(const fd_model *model, fd_state *state, const fd_shot *s
 fd_status fd_step(const fd_model *model, fd_state *state, const fd_shot *shot, int64_t n,
                   float *trace_row, void *stream);
 
-/* A whole shot: fd_begin_shot then steps 0..nt-1.  traces: device
- * [nt][nrec] or NULL.  ckpt: device buffer of ckpt_bytes bytes (at least
- * fd_sizes.checkpoints for (nt, ckpt_every)), or NULL; when given, the state
- * before steps 0, K, 2K, ... (K = ckpt_every >= 1) is saved for
- * fd_adjoint_gradient. */
+/* A whole shot: the time loop of Listing 3's run() (Section 7), i.e.
+ * fd_begin_shot then steps 0..nt-1, all enqueued on `stream`.  traces:
+ * device [nt][nrec] or NULL.  ckpt: device buffer of ckpt_bytes bytes (at
+ * least fd_sizes.checkpoints for (nt, ckpt_every)), or NULL; when given,
+ * the state before steps 0, K, 2K, ... (K = ckpt_every >= 1) is saved for
+ * fd_adjoint_gradient.  Errors (nothing is enqueued): FD_ERR_INVALID_ARG for
+ * NULL model/state/shot, a state of another model, an invalid shot, a short
+ * or misaligned checkpoint buffer; FD_ERR_UNSUPPORTED on a z-slab;
+ * FD_ERR_DEVICE if a launch fails (the state is then undefined). */
 fd_status fd_run_shot(const fd_model *model, fd_state *state, const fd_shot *shot,
                       float *traces, void *ckpt, size_t ckpt_bytes, int32_t ckpt_every,
                       void *stream);
@@ -212,7 +229,7 @@ fd_status fd_adjoint_gradient(const fd_model *model, const fd_shot *shot, const 
                               void *work, size_t work_bytes, double *grad_v, void *stream);
 
 /* Reverse-time-migration image of one shot (the imaging use the paper
- * names for this solver, Section 7): accumulates into image (device, dense
+ * names for this solver in its Discussion, Section 8): accumulates into image (device, dense
  * FP64, +=) the zero-lag correlation of the source wavefield w^n (the
  * field after the source addition of step n, recomputed from the
  * checkpoints) with the receiver wavefield z^k back-propagated from `data`
@@ -256,9 +273,15 @@ fd_status fd_rtm_image_shots(const fd_model *model, const fd_shot *const *shots,
                              double *image, void *stream);
 
 /* Copies P (which = 0) or Pold (which = 1) of the state, decoded to FP32,
- * into `out` (device, dense [nz][ny][nx]).  After k steps P holds the new
- * field of step k-1 plus the source addition of step k (none after the
- * last step, so after a whole shot it is the final wavefield). */
+ * into `out` (device, dense [nz][ny][nx], caller-owned): the "get" accessor
+ * of Listing 3's WaveSimulator (Section 7) and the first half of how an
+ * application ends in Section 5 (Start and stop: results leave the device
+ * container through an explicit copy; the caller then copies `out` to the
+ * host).  After k steps P holds the new field of step k-1 plus the source
+ * addition of step k (none after the last step, so after a whole shot it is
+ * the final wavefield).  Stream-ordered.  Errors: FD_ERR_INVALID_ARG for
+ * NULL arguments, `which` not 0 or 1, or a state that has not begun a shot;
+ * FD_ERR_DEVICE if the copy kernel fails to launch. */
 fd_status fd_get_wavefield(const fd_state *state, int32_t which, float *out, void *stream);
 
 /* Sets P (which = 0) or Pold (which = 1) of the state from `in` (device,
@@ -314,7 +337,10 @@ fd_status fd_step_batch(fd_batch_item *items, int32_t count, int32_t nsteps, voi
 fd_status fd_step_routines(const fd_model *model, fd_state *state, const fd_shot *shot, int64_t n,
                            float *trace_row, void *work, size_t work_bytes, void *stream);
 
-/* Message for the last non-OK status on this thread ("" if none). */
+/* Message for the last non-OK status on this thread ("" if none): the error
+ * side of the host/device boundary of Section 5 (Start and stop), across
+ * which every call above reports a status instead of throwing.  The string
+ * is owned by the library and valid until the next call on this thread. */
 const char *fd_last_error(void);
 
 /* Library version string. */

@@ -457,15 +457,26 @@ static int32_t storage_exponent(float m)
     return (int32_t)(ex - 1 - 11);
 }
 
+/* The integer nearest t >= 0, ties to even. */
+static double rne(double t)
+{
+    double k = floor(t);
+    double frac = t - k;
+    if (frac > 0.5 || (frac == 0.5 && fmod(k, 2.0) != 0.0)) k += 1.0;
+    return k;
+}
+
 /*
  * The model term c = (v dt/dh)^2 held as unsigned 16-bit fixed point with one
  * power-of-two scale (the 16-bit storage form's option to store the model in
- * 16 bits as well): with M the largest c, e is the exponent with
- * 2^(e-1) <= M < 2^e, each code is the integer nearest c 2^(16-e) (ties to
- * even), capped at 65535, and stands for code * 2^(e-16).  The rounding
- * decision is taken on the FP32 value of c, as the kernels take it.  Writes
- * the codes to q (may be NULL) and e to *e; replaces c by its decoded value
- * when `decode_in_place` is set.
+ * 16 bits as well): with M the largest c, e is the least exponent for which
+ * every code fits 16 bits, i.e. the one with 2^(e-1) <= M < 2^e, raised by
+ * one when M 2^(16-e) rounds up to 2^16 (M within half a code of 2^e).  Each
+ * code is the integer nearest c 2^(16-e) (ties to even) and stands for
+ * code * 2^(e-16), so |c - code 2^(e-16)| <= 2^(e-17) for every cell.  The
+ * rounding decision is taken on the FP32 value of c, as the kernels take it.
+ * Writes the codes to q (may be NULL) and e to *e; replaces c by its decoded
+ * value when `decode_in_place` is set.
  */
 void or_c_fixed16(float *c, int64_t n, uint16_t *q, int32_t *e, int decode_in_place)
 {
@@ -474,13 +485,10 @@ void or_c_fixed16(float *c, int64_t n, uint16_t *q, int32_t *e, int decode_in_pl
         if (c[i] > M) M = c[i];
     int ex = 0;
     frexpf(M, &ex); /* M = f 2^ex, 1/2 <= f < 1 */
+    if (rne(ldexp((double)M, 16 - ex)) > 65535.0) ex += 1;
     *e = ex;
     for (int64_t i = 0; i < n; ++i) {
-        double t = ldexp((double)c[i], 16 - ex); /* exact */
-        double k = floor(t);
-        double frac = t - k;
-        if (frac > 0.5 || (frac == 0.5 && fmod(k, 2.0) != 0.0)) k += 1.0;
-        if (k > 65535.0) k = 65535.0;
+        double k = rne(ldexp((double)c[i], 16 - ex)); /* the product is exact */
         if (q) q[i] = (uint16_t)k;
         if (decode_in_place) c[i] = (float)ldexp(k, ex - 16);
     }

@@ -205,12 +205,16 @@ class Twin:
         storage 1: numpy float16 (IEEE binary16, round to nearest even);
         storage 2: bfloat16 by round-to-nearest-even on the FP32 bit pattern.
         c_fixed16: c replaced by its 16-bit fixed-point value (codes
-        rint(c 2^(16-e)), at most 65535, with 2^(e-1) <= max c < 2^e)."""
+        rint(c 2^(16-e)) with e the least exponent that keeps every code
+        below 2^16: 2^(e-1) <= max c < 2^e, plus one if max c rounds to 2^16)."""
         f32 = np.float32
         c = ((self.v * self.p.dt / self.p.dh) ** 2).astype(f32)
         if c_fixed16:
             e = int(np.frexp(c.max())[1])
-            codes = np.minimum(np.rint(c.astype(np.float64) * 2.0 ** (16 - e)), 65535.0)
+            while np.rint(float(c.max()) * 2.0 ** (16 - e)) > 65535.0:
+                e += 1
+            codes = np.rint(c.astype(np.float64) * 2.0 ** (16 - e))
+            assert codes.max() <= 65535.0
             c = (codes * 2.0 ** (e - 16)).astype(f32)
         shape = self.p.shape
         # axis profiles rounded to FP32, multiplied in z, y, x order

@@ -410,6 +410,9 @@ fd_status fd_create_model(const fd_grid *grid, const float *velocity, void *mode
         const float cmax = (float)(qq * qq);
         int ex = 0;
         std::frexp(cmax, &ex);  // cmax = f 2^ex with f in [0.5, 1)
+        // a cmax within half a code of 2^ex would round to code 2^16: the
+        // next binade keeps every code in 16 bits and the error <= 2^(e-17)
+        if (std::nearbyint(std::ldexp((double)cmax, 16 - ex)) > 65535.0) ex += 1;
         m->c16_scale = std::ldexp(1.0f, ex - 16);
         m->c16_inv = std::ldexp(1.0f, 16 - ex);
         e = fdk::launch_model_c16(velocity, m->c16, L.nz * L.ny, (int32_t)L.nx, L.px,

@@ -144,3 +144,25 @@ def test_c_fixed16_codes_match_oracle_bitwise():
     np.testing.assert_array_equal(raw[:, :, :p.nx], q)
     assert not raw[:, :, p.nx:].any()
     assert q.max() > 32768          # the largest c sits in the top half of the code range
+
+
+def test_c_fixed16_codes_when_max_c_rounds_to_the_next_binade():
+    # c = (v dt/dh)^2 just below 0.25 (v just below 5000 m/s, 2D so the
+    # model is stable): in the bracket [2^-3, 2^-2) its code would round to
+    # 2^16, so the scale moves up one binade on both sides, and the codes
+    # still match the oracle's quantiser bit for bit.
+    import paper_2311_05038_amd as fd
+    p = fi.surface2d(30, 70, 4, seed=1)
+    v = fi.random_velocity(p.shape, 29, 1500, 4500)
+    v.reshape(-1)[17] = np.float32(4999.999)
+    r = p.dt / p.dh
+    c32 = ((v.astype(np.float64) * r) ** 2).astype(np.float32)
+    assert np.rint(float(c32.max()) * 2.0 ** 18) == 65536.0
+    model, _, _ = setup(p, v, storage=1, c_storage=fd.FD_C_FIXED16)
+    torch.cuda.synchronize()
+    px = (p.nx + 63) // 64 * 64
+    raw = model.buf[:p.nz * px * 2].cpu().numpy().view(np.uint16).reshape(p.nz, px)
+    q, e, dec = oracle.c_fixed16(c32)
+    assert e == -1
+    np.testing.assert_array_equal(raw[:, :p.nx], q)
+    assert np.all(np.abs(dec.astype(np.float64) - c32) <= 2.0 ** (e - 17))

@@ -110,12 +110,21 @@ def test_c_fixed16_codes_are_nearest_with_ties_to_even(orc):
     assert np.all(np.abs(qm[1:].astype(np.float64) - (k + 0.5)) == 0.5)
 
 
-def test_c_fixed16_cap_and_powers_of_two(orc):
-    # a largest c just below a power of two would round to 2^16: capped
+def test_c_fixed16_top_of_bracket_and_powers_of_two(orc):
+    # a largest c within half a code of a power of two would round to 2^16
+    # in its own bracket: the scale moves up one binade, and the error bound
+    # 2^(e-17) holds for that value too
     top = np.nextafter(np.float32(0.25), np.float32(0.0))
-    q, e, dec = orc.c_fixed16(np.array([top, 0.125, 0.0625, 0.0], dtype=np.float32))
+    vals = np.array([top, 0.125, 0.0625, 0.0], dtype=np.float32)
+    q, e, dec = orc.c_fixed16(vals)
+    assert e == -1 and q[0] == 32768
+    assert q[1] == 16384 and q[2] == 8192 and q[3] == 0
+    assert np.all(np.abs(dec.astype(np.float64) - vals) <= 2.0 ** (e - 17))
+    # just below that band the bracket stays: the largest code is 65535
+    t = np.float32((65535.25) * 2.0 ** -18)
+    q, e, dec = orc.c_fixed16(np.array([t, 0.1], dtype=np.float32))
     assert e == -2 and q[0] == 65535
-    assert q[1] == 32768 and q[2] == 16384 and q[3] == 0
+    assert abs(float(dec[0]) - float(t)) <= 2.0 ** (e - 17)
     # a largest c that is a power of two sits at the bottom of its bracket
     q, e, _ = orc.c_fixed16(np.array([0.125, 0.03125], dtype=np.float32))
     assert e == -2 and q[0] == 32768 and q[1] == 8192
