@@ -10,8 +10,11 @@ Parity status of each function (pins live in tests/test_oracle_*.py):
   coefficients  pinned: exact-rational moment solve, degree-10 error constant,
                 symbol range
   laplacian     pinned: polynomial exactness, symmetry
-  forward       pinned: 2D Green's function (with dt-halving convergence),
-                discrete energy conservation, reciprocity, NumPy twin
+  forward       pinned: 2D and 3D Green's functions (with dt-halving
+                convergence; the 3D one at offsets along each axis and a
+                diagonal), discrete energy conservation, growth above the
+                stability limit and reciprocity, each in 2D and in 3D; NumPy
+                twin
   sponge        pinned: a uniform damping factor g maps the damped update
                 exactly onto the undamped one for P^n / g^n (forward_G);
                 profile properties (1 off the band, decreasing into it,
