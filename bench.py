@@ -18,6 +18,9 @@ on the same GPU) add keys to the same line:
   slab     one eighth of the headline grid as a z-slab with ghost planes (the
            share of one device when the model is cut along z), with the
            ghost exchange timed beside it
+  cpu      the host back-end (libfd_cpu.so: the same ABI, OpenMP + AVX) on
+           the headline model for a few steps and on the 2D 256^2 case,
+           against a host stream probe of the step's access pattern
 """
 from __future__ import annotations
 
@@ -417,6 +420,47 @@ def slab_leg(nsteps: int = 200, ranks: int = 8):
     return res
 
 
+def cpu_leg(nsteps: int = 10):
+    """The host back-end on this machine's cores: Mcell-updates/s of the
+    fused FP32 step on the 512^3 headline model (a few steps) and of the
+    whole 256^2 / 500-step 2D shot, and the fraction of the host bandwidth
+    (fd_cpu_stream_probe: three FP32 streams read, one rewritten in place,
+    16 B per element, the step's own pattern) that the 3D step reaches at
+    16 algorithmic bytes per cell."""
+    import fd_inputs as fi
+    from helpers import grid_of, receivers_of
+    from paper_2311_05038_amd import cpu
+    out = dict(threads=cpu.threads(), isa=cpu.isa())
+    probe = cpu.stream_probe(1 << 27, 5)     # 3 x 512 MiB
+    out["stream_probe_gbs"] = round(probe, 1)
+    for name, p in (("layered3d_512", fi.layered3d(nt=nsteps + 2)), ("green2d_256", fi.green2d())):
+        v = p.velocity()
+        m = cpu.Model(grid_of(p), v)
+        s = m.new_state()
+        shot = cpu.Shot(p.src, p.wavelet(), receivers_of(p))
+        m.run_shot(s, shot)                  # warm-up (first touch)
+        best = float("inf")
+        for _ in range(3):
+            if p.ndim == 3:                  # steps 2.. of the shot, without the set-up
+                s.begin(shot)
+                s.step(shot, 0)
+                s.step(shot, 1)
+                t = time.perf_counter()
+                for n in range(2, p.nt):
+                    s.step(shot, n)
+            else:                            # the whole shot (fd_run_shot)
+                t = time.perf_counter()
+                m.run_shot(s, shot)
+            best = min(best, time.perf_counter() - t)
+        steps = p.nt - 2 if p.ndim == 3 else p.nt
+        mc = p.ncells * steps / best / 1e6
+        out[name] = dict(steps=steps, seconds=round(best, 4), mcell_per_s=round(mc, 1),
+                         alg_gbs=round(16 * mc / 1e3, 1), frac_of_probe=round(16 * mc / 1e3 / probe, 3))
+        del m, s
+    log(f"[bench] cpu leg: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -425,8 +469,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--probe-only", action="store_true",
                     help="only the 1 GiB copy probe (counter calibration)")
-    ap.add_argument("--legs", default="half,adjoint,serve,routines,slab",
-                    help="comma list of extra legs (half, adjoint, serve, routines, slab) or 'none'")
+    ap.add_argument("--legs", default="half,adjoint,serve,routines,slab,cpu",
+                    help="comma list of extra legs (half, adjoint, serve, routines, slab, cpu) "
+                         "or 'none'")
     ap.add_argument("--serve-requests", type=int, default=60)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -461,6 +506,8 @@ def main():
         extra["routines"] = routines_leg()
     if "slab" in legs:
         extra["slab"] = slab_leg()
+    if "cpu" in legs:
+        extra["cpu_backend"] = cpu_leg()
     cpu = cpu1 = None
     if not args.no_cpu:
         cpu = cpu_baseline()
