@@ -27,7 +27,10 @@ Parity status of each function (pins live in tests/test_oracle_*.py):
                 twin's forward map in m
   forward_half  pinned: conversions bit-exact against numpy float16 and torch
                 bfloat16; the FP32 arithmetic against the NumPy twin's
-                emulation
+                emulation (FP32 and 16-bit storage); the FP32-storage form
+                against the FP64 forward within the FP32 rounding bound, and
+                bit-identical to it on inputs whose arithmetic is exact in
+                FP32 (dyadic c, an impulse source)
   c_fixed16     pinned: scale bracket, nearest code with ties to even, the
                 cap, monotonicity; the twin's separate implementation; models
                 whose c values are codes already run unchanged
@@ -236,9 +239,10 @@ def image(grid: OrGrid, v: np.ndarray, wavelet: np.ndarray, nt: int, src, rec_in
 
 def forward_half(grid: OrGrid, storage: int, v: np.ndarray, wavelet: np.ndarray, nt: int,
                  src, rec_index, init_prev=None, init_cur=None, c_fixed16: bool = False):
-    """16-bit storage emulation (storage 1 = binary16, 2 = bfloat16).
-    init_prev/init_cur (FP32) replace the start state and its s[0] addition;
-    c_fixed16 holds c in 16-bit fixed point (c_fixed16())."""
+    """FP32-arithmetic emulation with FP32 (storage 0) or 16-bit storage
+    (1 = binary16, 2 = bfloat16).  init_prev/init_cur (FP32) replace the start
+    state and its s[0] addition; c_fixed16 (16-bit storage only) holds c in
+    16-bit fixed point (c_fixed16())."""
     v = np.ascontiguousarray(v, dtype=np.float32)
     ip = None if init_prev is None else np.ascontiguousarray(init_prev, dtype=np.float32)
     ic = None if init_cur is None else np.ascontiguousarray(init_cur, dtype=np.float32)
@@ -249,6 +253,8 @@ def forward_half(grid: OrGrid, storage: int, v: np.ndarray, wavelet: np.ndarray,
     rc = lib().or_forward_half(ctypes.byref(grid), storage, int(bool(c_fixed16)), _p(v), _p(wavelet), nt,
                                _src_linear(grid, src), rec.size, _p(rec), _p(ip), _p(ic),
                                _p(traces), _p(cur))
+    if rc == -2:
+        raise ValueError("oracle forward_half: storage must be 0, 1 or 2 (16-bit c needs 16-bit storage)")
     if rc != 0:
         raise MemoryError("oracle forward_half: allocation failed")
     return dict(traces=traces, cur=cur)

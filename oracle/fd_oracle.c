@@ -495,35 +495,48 @@ void or_c_fixed16(float *c, int64_t n, uint16_t *q, int32_t *e, int decode_in_pl
 }
 
 /*
- * The 16-bit storage form of or_forward.  Arithmetic in FP32, the order of
- * the terms as in or_forward.  Per step n:
- *   decode cur, prev; lap = L(cur); x = G (2 cur + c lap) - G^2 prev;
+ * The value a field holds once stored with exponent e: x itself in FP32
+ * storage (storage 0), else the 16-bit code RNE16(x 2^-e) decoded and scaled
+ * back by 2^e (exact: a power-of-two scale of a representable value).
+ */
+static float stored(int storage, float x, int32_t e)
+{
+    if (storage == 0) return x;
+    return ldexpf(dec(storage, enc(storage, ldexpf(x, -e))), e);
+}
+
+/*
+ * The reduced-precision forms of or_forward: arithmetic in FP32, the order of
+ * the terms as in or_forward, fields stored in FP32 (storage 0: the scheme's
+ * own FP32 rounding, nothing else) or in 16 bits (1 binary16, 2 bfloat16).
+ * Per step n:
+ *   cur, prev = the stored levels; lap = L(cur); x = G (2 cur + c lap) - G^2 prev;
  *   traces[n] sample x; x[src] += amp * s[n+1] (if n+1 < nt);
  *   e_new = floor(log2(max(M_cur, M_prev, |amp s[n+1]|))) - 11;
- *   store q = RNE16(x * 2^-e_new); M_new = max |x|.
+ *   store x (16-bit: q = RNE16(x * 2^-e_new)); M_new = max |x|.
  * The start state holds amp*s[0] at the source (stored the same way), so the
  * source addition happens once per level, as in or_forward.  Given
  * (init_prev, init_cur) instead, the start state is those FP32 fields, each
  * stored with exponent floor(log2 max|field|) - 11, and no s[0] is added.
  * c and G are the FP64 setup rounded to FP32, G as a product of FP32 axis
- * profiles (z, y, x order); with c_fixed16 set, c then takes its 16-bit
- * fixed-point value (or_c_fixed16).
+ * profiles (z, y, x order); with c_fixed16 set (16-bit fields only), c then
+ * takes its 16-bit fixed-point value (or_c_fixed16).
  */
 int or_forward_half(const or_grid *g, int storage, int c_fixed16, const float *v,
                     const float *wavelet, int64_t nt, int64_t src, int64_t nrec,
                     const int64_t *rec, const float *init_prev, const float *init_cur,
                     float *traces, float *final_cur)
 {
+    if (storage < 0 || storage > 2 || (storage == 0 && c_fixed16)) return -2;
     const int64_t N = g->nz * g->ny * g->nx;
     float *c = malloc(sizeof(float) * N), *G = malloc(sizeof(float) * N);
-    float *cur = malloc(sizeof(float) * N), *prev = malloc(sizeof(float) * N);
+    float *cur = malloc(sizeof(float) * N), *prev = calloc(N, sizeof(float));
     float *lap = malloc(sizeof(float) * N), *x = malloc(sizeof(float) * N);
-    uint16_t *qc = calloc(N, 2), *qp = calloc(N, 2), *qn = calloc(N, 2);
     double *gz = malloc(sizeof(double) * g->nz), *gy = malloc(sizeof(double) * g->ny);
     double *gx = malloc(sizeof(double) * g->nx);
-    if (!c || !G || !cur || !prev || !lap || !x || !qc || !qp || !qn || !gz || !gy || !gx) {
+    if (!c || !G || !cur || !prev || !lap || !x || !gz || !gy || !gx) {
         free(c); free(G); free(cur); free(prev); free(lap); free(x);
-        free(qc); free(qp); free(qn); free(gz); free(gy); free(gx);
+        free(gz); free(gy); free(gx);
         return -1;
     }
     const uint32_t f = g->sponge_faces;
@@ -553,8 +566,7 @@ int or_forward_half(const or_grid *g, int storage, int c_fixed16, const float *v
     const float amp = (float)source_amp(g);
     const int R = g->radius;
 
-    /* start state */
-    int32_t ec, ep = 0;
+    /* start state: cur and prev hold the stored levels (prev starts at zero) */
     float Mc, Mp = 0.0f;
     if (init_cur || init_prev) {
         Mc = 0.0f;
@@ -562,23 +574,18 @@ int or_forward_half(const or_grid *g, int storage, int c_fixed16, const float *v
             if (init_cur && fabsf(init_cur[i]) > Mc) Mc = fabsf(init_cur[i]);
             if (init_prev && fabsf(init_prev[i]) > Mp) Mp = fabsf(init_prev[i]);
         }
-        ec = storage_exponent(Mc);
-        ep = storage_exponent(Mp);
+        const int32_t ec = storage_exponent(Mc), ep = storage_exponent(Mp);
         for (int64_t i = 0; i < N; ++i) {
-            qc[i] = enc(storage, ldexpf(init_cur ? init_cur[i] : 0.0f, -ec));
-            qp[i] = enc(storage, ldexpf(init_prev ? init_prev[i] : 0.0f, -ep));
+            cur[i] = stored(storage, init_cur ? init_cur[i] : 0.0f, ec);
+            prev[i] = stored(storage, init_prev ? init_prev[i] : 0.0f, ep);
         }
     } else {
         float x0 = (nt > 0 && src >= 0) ? amp * wavelet[0] : 0.0f;
-        ec = storage_exponent(fabsf(x0));
-        if (src >= 0) qc[src] = enc(storage, ldexpf(x0, -ec));
+        for (int64_t i = 0; i < N; ++i) cur[i] = 0.0f;
+        if (src >= 0) cur[src] = stored(storage, x0, storage_exponent(fabsf(x0)));
         Mc = fabsf(x0);
     }
     for (int64_t n = 0; n < nt; ++n) {
-        for (int64_t i = 0; i < N; ++i) {
-            cur[i] = ldexpf(dec(storage, qc[i]), ec);
-            prev[i] = ldexpf(dec(storage, qp[i]), ep);
-        }
         /* FP32 Laplacian, zero edges, same term order as or_laplacian. */
 #pragma omp parallel for schedule(static)
         for (int64_t z = 0; z < g->nz; ++z)
@@ -606,26 +613,24 @@ int or_forward_half(const or_grid *g, int storage, int c_fixed16, const float *v
         if (src >= 0) x[src] += inj;
         float m = Mc > Mp ? Mc : Mp;
         if (fabsf(inj) > m) m = fabsf(inj);
-        int32_t en = storage_exponent(m);
+        const int32_t en = storage_exponent(m);
         float Mn = 0.0f;
+        /* the new level is stored over prev, which becomes the current level */
         for (int64_t i = 0; i < N; ++i) {
-            qn[i] = enc(storage, ldexpf(x[i], -en));
             float ax = fabsf(x[i]);
             if (ax > Mn) Mn = ax;
+            prev[i] = stored(storage, x[i], en);
         }
-        uint16_t *t = qp;
-        qp = qc;
-        qc = qn;
-        qn = t;
-        ep = ec;
-        ec = en;
+        float *t = prev;
+        prev = cur;
+        cur = t;
         Mp = Mc;
         Mc = Mn;
     }
     if (final_cur)
-        for (int64_t i = 0; i < N; ++i) final_cur[i] = ldexpf(dec(storage, qc[i]), ec);
+        for (int64_t i = 0; i < N; ++i) final_cur[i] = cur[i];
     free(c); free(G); free(cur); free(prev); free(lap); free(x);
-    free(qc); free(qp); free(qn); free(gz); free(gy); free(gx);
+    free(gz); free(gy); free(gx);
     return 0;
 }
 

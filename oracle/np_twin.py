@@ -200,8 +200,10 @@ class Twin:
         return gc
 
     def forward_half(self, wavelet, nt, storage: int, c_fixed16: bool = False):
-        """FP32 arithmetic with 16-bit storage and power-of-two field scales.
+        """FP32 arithmetic with FP32 or 16-bit storage and power-of-two field
+        scales.
 
+        storage 0: FP32 storage (no rounding beyond the FP32 arithmetic);
         storage 1: numpy float16 (IEEE binary16, round to nearest even);
         storage 2: bfloat16 by round-to-nearest-even on the FP32 bit pattern.
         c_fixed16: c replaced by its 16-bit fixed-point value (codes
@@ -234,6 +236,8 @@ class Twin:
         amp = f32(self.amp)
 
         def enc(x):
+            if storage == 0:
+                return x.astype(f32)
             if storage == 1:
                 return x.astype(np.float16)
             u = x.astype(f32).view(np.uint32).astype(np.uint64)
@@ -243,6 +247,8 @@ class Twin:
             return (kept + up).astype(np.uint16)
 
         def dec(q):
+            if storage == 0:
+                return q.astype(f32)
             if storage == 1:
                 return q.astype(f32)
             return (q.astype(np.uint32) << 16).view(f32)
