@@ -21,19 +21,36 @@ constexpr float kA2 = (float)(-1.0 / 5.0);
 constexpr float kA3 = (float)(8.0 / 315.0);
 constexpr float kA4 = (float)(-1.0 / 560.0);
 
-// sum_k a_k (u_{-k} + u_{+k}), k = 1..4.  The library is built with
-// -ffp-contract=off; every fused multiply-add is written out, so all kernel
-// variants round identically.
+// sum_k a_k (u_{-k} + u_{+k}), k = 1..4 (the 16-bit steps add a_0 u
+// afterwards).  The library is built with -ffp-contract=off; every fused
+// multiply-add is written out, so all kernel variants round identically.
 __device__ __forceinline__ float stencil_taps(float m4, float m3, float m2, float m1, float p1,
                                               float p2, float p3, float p4)
 {
     return fmaf(kA4, m4 + p4, fmaf(kA3, m3 + p3, fmaf(kA2, m2 + p2, kA1 * (m1 + p1))));
 }
 
-// new = G (2 cur + c lap) - G^2 prev
+// The whole second difference along one axis, a_0 u + sum_k a_k (u_{-k} +
+// u_{+k}), evaluated as sum_k a_k ((u_{-k} - u) + (u_{+k} - u)) (equal, since
+// a_0 = -2 sum_k a_k).  For a smooth field the differences are small and
+// nearly exact, so the rounding error is relative to the derivative rather
+// than to u itself; summing a_0 u with the taps instead cancels ~6.5 |u| down
+// to the derivative, and that error, carried by the leapfrog's slowly
+// decaying long-wavelength modes, dominated the FP32 field error (about ten
+// times the difference form's over a few hundred steps).
+__device__ __forceinline__ float axis_d2(float m4, float m3, float m2, float m1, float u, float p1,
+                                         float p2, float p3, float p4)
+{
+    return fmaf(kA4, (m4 - u) + (p4 - u),
+                fmaf(kA3, (m3 - u) + (p3 - u), fmaf(kA2, (m2 - u) + (p2 - u), kA1 * ((m1 - u) + (p1 - u)))));
+}
+
+// new = G (2 cur + c lap) - G^2 prev, evaluated as G (cur + (c lap + (cur -
+// G prev))): the small increment c lap + (cur - G prev) is formed before the
+// large cur is added (G = 1 off the damping band).
 __device__ __forceinline__ float leapfrog(float G, float ctr, float c, float lap, float prev)
 {
-    return fmaf(G, fmaf(c, lap, 2.0f * ctr), -(G * G) * prev);
+    return G * (ctr + fmaf(c, lap, fmaf(-G, prev, ctr)));
 }
 
 enum Mode : int {

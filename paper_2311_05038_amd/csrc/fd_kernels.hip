@@ -296,11 +296,20 @@ __device__ __forceinline__ void step2d_tile(const StepArgs &a, int tx, int tz,
 #pragma unroll
         for (int v = 0; v < VX; ++v) {
             const int li = 4 + lane * VX + v;
-            const float lx = stencil_taps(rw[li - 4], rw[li - 3], rw[li - 2], rw[li - 1],
-                                          rw[li + 1], rw[li + 2], rw[li + 3], rw[li + 4]);
-            const float lz = stencil_taps(q[0][v], q[1][v], q[2][v], q[3][v], q[5][v], q[6][v],
-                                          q[7][v], q[8][v]);
-            const float lap = fmaf(2.0f * kA0, q[4][v], lz + lx);
+            float lap;
+            if constexpr (ST == kF32) {
+                const float lx = axis_d2(rw[li - 4], rw[li - 3], rw[li - 2], rw[li - 1], q[4][v],
+                                         rw[li + 1], rw[li + 2], rw[li + 3], rw[li + 4]);
+                const float lz = axis_d2(q[0][v], q[1][v], q[2][v], q[3][v], q[4][v], q[5][v],
+                                         q[6][v], q[7][v], q[8][v]);
+                lap = lz + lx;
+            } else {
+                const float lx = stencil_taps(rw[li - 4], rw[li - 3], rw[li - 2], rw[li - 1],
+                                              rw[li + 1], rw[li + 2], rw[li + 3], rw[li + 4]);
+                const float lz = stencil_taps(q[0][v], q[1][v], q[2][v], q[3][v], q[5][v], q[6][v],
+                                              q[7][v], q[8][v]);
+                lap = fmaf(2.0f * kA0, q[4][v], lz + lx);
+            }
             G[v] = gzz * gxv[v];
             nw[v] = update<ST>(G[v], q[4][v], cc[v], lap, pc[v], h);
             lp[v] = MODE == kAdj ? q[4][v] : lap;
@@ -604,16 +613,14 @@ __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
     #pragma unroll
                 for (int v = 0; v < VX; ++v) {
                     const int li = (trow + NW * RPW * j + 4) * LW + 4 + col * VX + v;
-                    const float lx = stencil_taps(P[li - 4], P[li - 3], P[li - 2], P[li - 1], P[li + 1],
-                                                  P[li + 2], P[li + 3], P[li + 4]);
-                    const float lyv = stencil_taps(P[li - 4 * LW], P[li - 3 * LW], P[li - 2 * LW],
-                                                   P[li - LW], P[li + LW], P[li + 2 * LW],
-                                                   P[li + 3 * LW], P[li + 4 * LW]);
-                    const float lz = stencil_taps(q[j][0][v], q[j][1][v],
-                                                  q[j][2][v], q[j][3][v],
-                                                  q[j][5][v], q[j][6][v],
-                                                  q[j][7][v], q[j][8][v]);
-                    const float lap = fmaf(3.0f * kA0, q[j][4][v], lz + (lyv + lx));
+                    const float u = q[j][4][v];
+                    const float lx = axis_d2(P[li - 4], P[li - 3], P[li - 2], P[li - 1], u, P[li + 1],
+                                             P[li + 2], P[li + 3], P[li + 4]);
+                    const float lyv = axis_d2(P[li - 4 * LW], P[li - 3 * LW], P[li - 2 * LW], P[li - LW], u,
+                                              P[li + LW], P[li + 2 * LW], P[li + 3 * LW], P[li + 4 * LW]);
+                    const float lz = axis_d2(q[j][0][v], q[j][1][v], q[j][2][v], q[j][3][v], u,
+                                             q[j][5][v], q[j][6][v], q[j][7][v], q[j][8][v]);
+                    const float lap = lz + (lyv + lx);
                     G[v] = (gzz * gyv[j]) * gxv[v];
                     nw[v] = update<ST>(G[v], q[j][4][v], cc[j][v], lap, pc[j][v], h);
                     lp[v] = MODE == kAdj ? q[j][4][v] : lap;

@@ -15,7 +15,7 @@ namespace fdk {
 
 namespace {
 
-// Taps of the second difference along a strided axis (z, or y in 3D).  A
+// Second difference along a strided axis (z, or y in 3D).  A
 // thread owns 4 adjacent x cells of one line along the axis and walks a
 // chunk of it with a 9-deep register queue, so each input value is read
 // once.  Work item w = (outer line, chunk, x group), x group fastest, so the
@@ -47,10 +47,10 @@ __global__ __launch_bounds__(256) void k_deriv_axis(const float *__restrict__ in
     for (int32_t k = k0; k < k1; ++k) {
         q[8] = ld(k + 4);
         float4 r;
-        r.x = stencil_taps(q[0].x, q[1].x, q[2].x, q[3].x, q[5].x, q[6].x, q[7].x, q[8].x);
-        r.y = stencil_taps(q[0].y, q[1].y, q[2].y, q[3].y, q[5].y, q[6].y, q[7].y, q[8].y);
-        r.z = stencil_taps(q[0].z, q[1].z, q[2].z, q[3].z, q[5].z, q[6].z, q[7].z, q[8].z);
-        r.w = stencil_taps(q[0].w, q[1].w, q[2].w, q[3].w, q[5].w, q[6].w, q[7].w, q[8].w);
+        r.x = axis_d2(q[0].x, q[1].x, q[2].x, q[3].x, q[4].x, q[5].x, q[6].x, q[7].x, q[8].x);
+        r.y = axis_d2(q[0].y, q[1].y, q[2].y, q[3].y, q[4].y, q[5].y, q[6].y, q[7].y, q[8].y);
+        r.z = axis_d2(q[0].z, q[1].z, q[2].z, q[3].z, q[4].z, q[5].z, q[6].z, q[7].z, q[8].z);
+        r.w = axis_d2(q[0].w, q[1].w, q[2].w, q[3].w, q[4].w, q[5].w, q[6].w, q[7].w, q[8].w);
         if constexpr (STREAM)
             stp_stream<float, 4>(obase + (int64_t)k * axis_stride, Pack<float, 4>{{r.x, r.y, r.z, r.w}});
         else
@@ -60,7 +60,7 @@ __global__ __launch_bounds__(256) void k_deriv_axis(const float *__restrict__ in
     }
 }
 
-// Taps of the second difference along x: a thread owns 4 adjacent cells of
+// Second difference along x: a thread owns 4 adjacent cells of
 // a row and loads only those; the 4 values on each side come from the
 // neighbouring lanes through the wave (lanes hold consecutive groups of a
 // row), and only the wave's first and last lanes load them.  Cells past nx
@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_deriv_x(const float *__restrict__ in, f
     float o[4];
 #pragma unroll
     for (int v = 0; v < 4; ++v)
-        o[v] = stencil_taps(u[v], u[v + 1], u[v + 2], u[v + 3], u[v + 5], u[v + 6], u[v + 7], u[v + 8]);
+        o[v] = axis_d2(u[v], u[v + 1], u[v + 2], u[v + 3], u[v + 4], u[v + 5], u[v + 6], u[v + 7], u[v + 8]);
     if constexpr (STREAM)
         stp_stream<float, 4>(out + row * px + x0, Pack<float, 4>{{o[0], o[1], o[2], o[3]}});
     else
@@ -106,7 +106,7 @@ __global__ __launch_bounds__(256) void k_deriv_x(const float *__restrict__ in, f
 }
 
 // Time update with the sponge, from the materialised derivative fields:
-//   L = a0 D cur + Pzz + (Pyy + Pxx)      (2D: a0 2 cur + Pzz + Pxx)
+//   L = Pzz + (Pyy + Pxx)      (2D: Pzz + Pxx)
 //   new = G (2 cur + c L) - G^2 prev,  G = gz gy gx,
 // written over prev, with the receivers sampling `new`.
 // STREAM (all three kinds of routine kernels): non-temporal accesses, for
@@ -151,9 +151,9 @@ __global__ __launch_bounds__(256) void k_time(StepArgs a, const float *__restric
         const float gx = x < a.nx ? a.gx[x] : 0.0f;
         float lap;
         if constexpr (NDIM == 3)
-            lap = fmaf(3.0f * kA0, pv[v], zv[v] + (yv[v] + xv[v]));
+            lap = zv[v] + (yv[v] + xv[v]);
         else
-            lap = fmaf(2.0f * kA0, pv[v], zv[v] + xv[v]);
+            lap = zv[v] + xv[v];
         nw[v] = x < a.nx ? leapfrog(gzy * gx, pv[v], cv[v], lap, qv[v]) : 0.0f;
     }
     if (a.trace_row != nullptr) {

@@ -66,6 +66,7 @@ struct Scalar {
     static void st(float *p, V v) { *p = v; }
     static V set1(float a) { return a; }
     static V add(V a, V b) { return a + b; }
+    static V sub(V a, V b) { return a - b; }
     static V mul(V a, V b) { return a * b; }
     static V fma(V a, V b, V c) { return std::fma(a, b, c); }
     static V neg(V a) { return -a; }

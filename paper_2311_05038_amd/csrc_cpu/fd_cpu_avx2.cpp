@@ -12,6 +12,7 @@ struct Avx2 {
     static void st(float *p, V v) { _mm256_storeu_ps(p, v); }
     static V set1(float a) { return _mm256_set1_ps(a); }
     static V add(V a, V b) { return _mm256_add_ps(a, b); }
+    static V sub(V a, V b) { return _mm256_sub_ps(a, b); }
     static V mul(V a, V b) { return _mm256_mul_ps(a, b); }
     static V fma(V a, V b, V c) { return _mm256_fmadd_ps(a, b, c); }
     static V neg(V a) { return _mm256_xor_ps(a, _mm256_set1_ps(-0.0f)); }

@@ -12,6 +12,7 @@ struct Avx512 {
     static void st(float *p, V v) { _mm512_storeu_ps(p, v); }
     static V set1(float a) { return _mm512_set1_ps(a); }
     static V add(V a, V b) { return _mm512_add_ps(a, b); }
+    static V sub(V a, V b) { return _mm512_sub_ps(a, b); }
     static V mul(V a, V b) { return _mm512_mul_ps(a, b); }
     static V fma(V a, V b, V c) { return _mm512_fmadd_ps(a, b, c); }
     static V neg(V a)

@@ -7,10 +7,11 @@
 // the fused form of Listing 3's fd_pzz, fd_pxx and fd_time (Section 7), with
 // L the 8th-order second difference summed over the axes (weights
 // a = (-205/72, 8/5, -1/5, 8/315, -1/560)).  Every multiply-add is an exact
-// fused one and the order of operations is fixed (taps of one axis as
-// a4 (u-4 + u+4) + (a3 (u-3 + u+3) + (a2 (u-2 + u+2) + a1 (u-1 + u+1))),
-// axes as z + (y + x), then the centre), so the result does not depend on
-// the vector width.
+// fused one and the order of operations is fixed, so the result does not
+// depend on the vector width: each axis as
+// a4 d4 + (a3 d3 + (a2 d2 + a1 d1)) with dk = (u-k - u) + (u+k - u) (the
+// centre weight a0 = -2 (a1 + a2 + a3 + a4) folded into the differences),
+// axes as z + (y + x), and the update as G (P + (c L + (P - G Pold))).
 #pragma once
 
 #include <cstddef>
@@ -18,7 +19,6 @@
 
 namespace fdcpu {
 
-constexpr float kA0 = (float)(-205.0 / 72.0);
 constexpr float kA1 = (float)(8.0 / 5.0);
 constexpr float kA2 = (float)(-1.0 / 5.0);
 constexpr float kA3 = (float)(8.0 / 315.0);
@@ -39,44 +39,40 @@ struct Row {
 };
 
 template <class O>
-inline typename O::V taps(typename O::V m4, typename O::V m3, typename O::V m2, typename O::V m1,
-                          typename O::V p1, typename O::V p2, typename O::V p3, typename O::V p4)
+inline typename O::V dsum(typename O::V m, typename O::V u, typename O::V p)
 {
-    using V = typename O::V;
-    const V t1 = O::mul(O::set1(kA1), O::add(m1, p1));
-    const V t2 = O::fma(O::set1(kA2), O::add(m2, p2), t1);
-    const V t3 = O::fma(O::set1(kA3), O::add(m3, p3), t2);
-    return O::fma(O::set1(kA4), O::add(m4, p4), t3);
+    return O::add(O::sub(m, u), O::sub(p, u));
 }
 
+// The second difference along one axis, from the centre value u.
 template <class O>
-inline typename O::V axis_taps(const float *p, ptrdiff_t s)
+inline typename O::V axis_d2(const float *p, ptrdiff_t s, typename O::V u)
 {
-    return taps<O>(O::ld(p - 4 * s), O::ld(p - 3 * s), O::ld(p - 2 * s), O::ld(p - s), O::ld(p + s),
-                   O::ld(p + 2 * s), O::ld(p + 3 * s), O::ld(p + 4 * s));
+    using V = typename O::V;
+    const V t1 = O::mul(O::set1(kA1), dsum<O>(O::ld(p - s), u, O::ld(p + s)));
+    const V t2 = O::fma(O::set1(kA2), dsum<O>(O::ld(p - 2 * s), u, O::ld(p + 2 * s)), t1);
+    const V t3 = O::fma(O::set1(kA3), dsum<O>(O::ld(p - 3 * s), u, O::ld(p + 3 * s)), t2);
+    return O::fma(O::set1(kA4), dsum<O>(O::ld(p - 4 * s), u, O::ld(p + 4 * s)), t3);
 }
 
 template <class O, int NDIM>
 inline void step_row(const Row &r)
 {
     using V = typename O::V;
-    const V kc = O::set1((float)NDIM * kA0);
-    const V two = O::set1(2.0f);
     const V gzy = O::set1(r.gzy);
     for (int64_t x = 0; x < r.nx; x += O::W) {
         const float *p = r.P + x;
         const V ctr = O::ld(p);
-        const V lx = axis_taps<O>(p, 1);
-        const V lz = axis_taps<O>(p, r.zs);
-        V sum;
+        const V lx = axis_d2<O>(p, 1, ctr);
+        const V lz = axis_d2<O>(p, r.zs, ctr);
+        V lap;
         if constexpr (NDIM == 3)
-            sum = O::add(lz, O::add(axis_taps<O>(p, r.ys), lx));
+            lap = O::add(lz, O::add(axis_d2<O>(p, r.ys, ctr), lx));
         else
-            sum = O::add(lz, lx);
-        const V lap = O::fma(kc, ctr, sum);
+            lap = O::add(lz, lx);
         const V G = O::mul(gzy, O::ld(r.gx + x));
-        const V GG = O::neg(O::mul(G, G));
-        V nw = O::fma(G, O::fma(O::ld(r.c + x), lap, O::mul(two, ctr)), O::mul(GG, O::ld(r.Q + x)));
+        const V inc = O::fma(O::ld(r.c + x), lap, O::fma(O::neg(G), O::ld(r.Q + x), ctr));
+        V nw = O::mul(G, O::add(ctr, inc));
         if (x + O::W > r.nx) nw = O::keep(nw, (int)(r.nx - x));  // cells past the row stay 0
         O::st(r.Q + x, nw);
     }

@@ -6,10 +6,12 @@ hours for this run, so only samples are kept).
 
 Errors are stated (printed) and bounded, per storage, for the traces (and
 their norm), the field norm, and the sampled final cells and 16^3 block sums:
-  FP32: 1e-4 / 1e-4 / 5e-4.  The traces meet the 1e-4 bound (7e-6), but
-        FP32 rounding of the leapfrog update keeps accumulating in the
-        late-time field: after 2000 steps the sampled cells sit at 1.5e-4 and
-        the block sums (a smooth, low-wavenumber view) at 2.5e-4.
+  FP32: 1e-4 / 1e-4 / 1e-4 (measured 7.7e-7, 7.9e-8, 3.2e-6 / 1.6e-6).
+        The kernels take each axis's second difference as a weighted sum of
+        differences from the centre value; with the centre weight summed
+        against the taps instead, the cancellation error carried by the
+        slowly decaying long-wavelength modes left the late-time field at
+        1.5e-4 (cells) and 2.5e-4 (block sums).
   FP16: 1e-2 / 1e-2 / 5e-2 (measured 5.7e-3, 2.8e-4, 2.1e-2 / 2.6e-2).
   BF16: 8e-2 / 2e-1 / 1.0 (measured 6.4e-2, 1.0e-1, 0.52 / 0.89): with 8
         significand bits the stored fields lose the late-time field to
@@ -31,7 +33,7 @@ pytestmark = pytest.mark.gpu
 
 TRACE_BOUND = {0: 1e-4, 1: 1e-2, 2: 8e-2}
 NORM_BOUND = {0: 1e-4, 1: 1e-2, 2: 2e-1}
-FIELD_BOUND = {0: 5e-4, 1: 5e-2, 2: 1.0}
+FIELD_BOUND = {0: 1e-4, 1: 5e-2, 2: 1.0}
 NAME = {0: "fp32", 1: "fp16", 2: "bf16"}
 
 
