@@ -18,6 +18,8 @@ on the same GPU) add keys to the same line:
   slab     one eighth of the headline grid as a z-slab with ghost planes (the
            share of one device when the model is cut along z), with the
            ghost exchange timed beside it
+  small2d  single small 2D shots (the 256^2 case, a 1024^2 shot) against 16
+           of them batched in one launch per step
   cpu      the host back-end (libfd_cpu.so: the same ABI, OpenMP + AVX) on
            the headline model for a few steps and on the 2D 256^2 case,
            against a host stream probe of the step's access pattern
@@ -57,71 +59,124 @@ def headline(steps: int, warmup: int):
         log(f"[bench] warmup {i} done")
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
+    # one event per shot boundary as well: the spread of the single shots
+    marks = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     t0.record(stream)
+    marks[0].record(stream)
     for i in range(steps):
         model.run_shot(state, shot, traces)
+        marks[i + 1].record(stream)
     t1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     ms = t0.elapsed_time(t1)
+    shot_ms = sorted(marks[i].elapsed_time(marks[i + 1]) for i in range(steps))
     cells = p.ncells * p.nt
     mcell = cells * steps / (ms * 1e-3) / 1e6
     per_launch_s = ms * 1e-3 / (steps * p.nt)
     alg_bytes = 16.0 * p.ncells
     achieved = alg_bytes / per_launch_s / 1e9
     log(f"[bench] {steps} shots in {ms:.1f} ms (wall {wall:.2f} s): {mcell:.0f} Mcell/s, "
-        f"{achieved:.0f} GB/s algorithmic")
-    return dict(p=p, ms=ms, mcell=mcell, achieved=achieved, per_launch_us=per_launch_s * 1e6)
+        f"{achieved:.0f} GB/s algorithmic; single shots {shot_ms[0]:.1f} .. {shot_ms[-1]:.1f} ms")
+    med = shot_ms[steps // 2] if steps % 2 else 0.5 * (shot_ms[steps // 2 - 1] + shot_ms[steps // 2])
+    stats = dict(median=round(med, 3), min=round(shot_ms[0], 3), max=round(shot_ms[-1], 3), n=steps)
+    return dict(p=p, ms=ms, mcell=mcell, achieved=achieved, per_launch_us=per_launch_s * 1e6, shot_ms=stats)
+
+
+def _timed_probe(kind: int, arrays, n: int, reps: int) -> float:
+    """Median microseconds of one fd_stream_probe launch (HIP events on the
+    stream it runs on)."""
+    import statistics
+    import torch
+    from paper_2311_05038_amd import _abi
+    s = torch.cuda.current_stream()
+    a, b, out = arrays
+    bp = b.data_ptr() if b is not None else None
+    for _ in range(3):
+        _abi.fd_stream_probe(kind, a.data_ptr(), bp, out.data_ptr(), n, s.cuda_stream)
+    ts = []
+    for _ in range(reps):
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        _abi.fd_stream_probe(kind, a.data_ptr(), bp, out.data_ptr(), n, s.cuda_stream)
+        e1.record(s)
+        e1.synchronize()
+        ts.append(e0.elapsed_time(e1) * 1e3)
+    return statistics.median(ts)
 
 
 def copy_probe(nbytes: int = 1 << 30, reps: int = 20):
-    """A plain streaming kernel of known size (elementwise negation: 4 B read
-    and 4 B written per element, 1 GiB each way): the practical HBM roof (the
-    role BabelStream plays in the paper's roofline) and the calibration
-    kernel for the rocprofv3 byte counters."""
+    """The library's copy probe (fd_stream_probe kind 0: 1 GiB read and 1 GiB
+    written, non-temporal, each XCD streaming one contiguous eighth): the
+    practical HBM roof of a plain stream, and the calibration kernel for the
+    rocprofv3 byte counters."""
     import torch
-    a = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
-    b = torch.empty_like(a)
-    for _ in range(3):
-        torch.neg(a, out=b)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(reps):
-        torch.neg(a, out=b)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1)
-    return dict(bytes_per_copy=2 * nbytes, gbs=2 * nbytes * reps / (ms * 1e-3) / 1e9)
+    n = nbytes // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    out = torch.empty_like(a)
+    us = _timed_probe(0, (a, None, out), n, reps)
+    del a, out
+    torch.cuda.empty_cache()
+    return dict(bytes_per_copy=2 * nbytes, us=us, gbs=2 * nbytes / (us * 1e-6) / 1e9)
 
 
 def stream_probe(cells: int = 512 ** 3, reps: int = 20):
-    """The stencil step's traffic without the stencil: d = a + b * c
-    elementwise over three FP32 inputs and one output of the 512^3 size
-    (torch.addcmul: 12 B read + 4 B written per element), i.e. the practical
-    roof of a 3-read / 1-write stream on this GPU."""
+    """The step's traffic without the stencil (fd_stream_probe kind 1: out =
+    a + b * out over three FP32 arrays of the 512^3 size, 12 B read and 4 B
+    written per element in place, the step kernel's accesses): the practical
+    roof of the FP32 step on this GPU."""
     import torch
     a = torch.ones(cells, dtype=torch.float32, device="cuda")
     b = torch.ones_like(a)
-    c = torch.ones_like(a)
-    d = torch.empty_like(a)
-    for _ in range(3):
-        torch.addcmul(a, b, c, out=d)
-    t0 = torch.cuda.Event(enable_timing=True)
-    t1 = torch.cuda.Event(enable_timing=True)
-    torch.cuda.synchronize()
-    t0.record()
-    for _ in range(reps):
-        torch.addcmul(a, b, c, out=d)
-    t1.record()
-    torch.cuda.synchronize()
-    ms = t0.elapsed_time(t1) / reps
-    del a, b, c, d
+    out = torch.zeros_like(a)
+    us = _timed_probe(1, (a, b, out), cells, reps)
+    del a, b, out
     torch.cuda.empty_cache()
-    return dict(us=ms * 1e3, gbs=16 * cells / (ms * 1e-3) / 1e9)
+    return dict(us=us, gbs=16 * cells / (us * 1e-6) / 1e9)
+
+
+def small2d_leg(reps: int = 5):
+    """Small 2D shots, where a step is too small to fill the GPU: the 256^2
+    Green's-function case (500 steps) and a 1024^2 shot (2000 steps) as
+    single fd_run_shot calls (one launch per step), and 16 shots of the 256^2
+    case in one fd_run_shots call (one batched launch per step)."""
+    import statistics
+    import torch
+    import fd_inputs as fi
+    from helpers import setup
+    out = {}
+    s = torch.cuda.current_stream()
+
+    def timed(fn, steps, cells):
+        fn()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(s)
+            fn()
+            e1.record(s)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e3)
+        us = statistics.median(ts)
+        return dict(us_per_step=round(us / steps, 2), mcell_per_s=round(cells * steps / us, 1),
+                    spread_pct=round(100 * (max(ts) - min(ts)) / us, 1))
+
+    for name, p in (("green2d_256", fi.green2d()), ("surface2d_1024", fi.surface2d(1024, 1024, 2000, seed=5))):
+        model, state, shot = setup(p)
+        tr = torch.empty((p.nt, p.receivers.count), device="cuda")
+        out[name] = timed(lambda: model.run_shot(state, shot, tr), p.nt, p.ncells)
+    p = fi.green2d()
+    model, _, shot = setup(p)
+    states = [model.new_state() for _ in range(16)]
+    shots = [shot] * 16
+    out["green2d_256_x16_batched"] = timed(lambda: model.run_shots(states, shots), p.nt, 16 * p.ncells)
+    log(f"[bench] small 2D: {out}")
+    return out
 
 
 def half_leg(nt: int = 2000):
@@ -211,53 +266,88 @@ def adjoint_leg(nt: int = 2000, every: int = 50):
     return out
 
 
-def serve_leg(n_requests: int = 60, seed: int = 50):
-    """A Poisson stream (50 shots/s) of 2D shots on grids drawn from
-    512^2..2048x4096: continuous batching vs sequential plain FP32 runs."""
+def serve_leg(n_requests: int = 1000, seed: int = 50, n_sub: int = 500, sub_frac: float = 0.7):
+    """Poisson streams of 2D shots on grids drawn from 512^2..2048x4096 (nt
+    1000..4000), each shot with its own seeded random-field velocity model
+    (generated on the device before any clock starts): continuous batching
+    against sequential plain FP32 runs of the same arrival trace.  Two
+    rates: 50 shots/s (n_requests shots; above what the device sustains, so
+    the queue grows), and sub_frac of the sustained rate the batched run
+    measured (the first n_sub shots on a fresh seeded trace)."""
     import numpy as np
     import torch
     import fd_inputs as fi
     import paper_2311_05038_amd as fd
     from paper_2311_05038_amd.serve import Request, Scheduler, TorchDevice, summarize
     reqs_in = fi.serving_stream(n_requests, seed=seed)
-    K = 4
-    base = [torch.from_numpy(fi.grf_velocity((2048, 4096), seed * 100 + k)).cuda() for k in range(K)]
+    t_gen = time.perf_counter()
+    vel = {}
+    for r in reqs_in:
+        vel[r.rid] = fi.grf_velocity_torch((r.nz, r.nx), r.seed, device="cuda").reshape(-1)
+        if (r.rid + 1) % 200 == 0:
+            torch.cuda.synchronize()
+            log(f"[bench] serve: {r.rid + 1} models generated ({time.perf_counter() - t_gen:.1f} s)")
+    torch.cuda.synchronize()
+    log(f"[bench] serve: {n_requests} seeded models in {time.perf_counter() - t_gen:.1f} s")
     wav_all = torch.from_numpy(fi.ricker(10.0, 1e-3, 4000)).cuda()
 
     def make_inputs(req):
         p = fi.surface2d(req.nz, req.nx, req.nt, req.rid)
         g = fd.Grid(ndim=2, nz=p.nz, ny=1, nx=p.nx, dh=p.dh, dt=p.dt,
                     sponge_width=p.sponge_width, sponge_faces=p.sponge_faces)
-        v = base[req.rid % K][: p.nz, : p.nx].contiguous().reshape(-1)
         r = p.receivers
         shot = fd.Shot(p.src, wav_all[: p.nt], fd.Receivers(r.z0, r.y0, r.x0, r.nz, r.ny, r.nx))
-        return g, v, shot
+        return g, vel[req.rid], shot
 
-    reqs = [Request(r.rid, r.arrival, r.nz, r.nx, r.nt) for r in reqs_in]
-    cells = {r.rid: r.nz * r.nx * r.nt for r in reqs}
-    res = {}
-    # "batched": the earliest-arrived resident shot and then the shots with
-    # the least remaining work advance, enough of them to give each launch
-    # 12 M cells per step, the others wait resident; "batched_all": every
-    # admitted shot advances in every launch
-    warm = [Request(i, 0.0, 512 + 256 * i, 1024, 200) for i in range(4)]
+    cells = {r.rid: r.nz * r.nx * r.nt for r in reqs_in}
+    warm = [Request(r.rid, 0.0, r.nz, r.nx, 200) for r in reqs_in[:4]]
     Scheduler(TorchDevice(make_inputs, batched=True), hbm_budget=200 << 30).run(warm)
     Scheduler(TorchDevice(make_inputs, batched=False), max_slots=1, policy="all",
               hbm_budget=200 << 30).run(warm)
-    for name, batched, slots, policy in (("batched", True, 64, "srpt_oldest"),
-                                         ("batched_all", True, 16, "all"),
-                                         ("sequential", False, 1, "all")):
-        torch.cuda.synchronize()
-        sch = Scheduler(TorchDevice(make_inputs, batched=batched), max_slots=slots,
-                        hbm_budget=200 << 30, chunk=25, policy=policy, launch_cells=12 << 20)
-        out = sch.run(reqs)
-        res[name] = {k: (round(v, 4) if isinstance(v, float) else v)
-                     for k, v in summarize(out, cells.get).items()}
-        res[name]["peak_slots"] = sch.peak_slots
-        log(f"[bench] serve {name}: {res[name]}")
-    offered = sum(cells.values()) / (reqs[-1].arrival - reqs[0].arrival)
-    res["offered_gcell_per_s"] = round(offered / 1e9, 1)
-    res["workload"] = f"serving stream: {n_requests} Poisson shots at 50/s, 512^2..2048x4096, nt 1000..4000"
+
+    def run_pair(reqs, tag):
+        out = {}
+        last = [time.perf_counter()]
+
+        def progress(done, total):
+            if time.perf_counter() - last[0] > 10.0 or done == total:
+                last[0] = time.perf_counter()
+                log(f"[bench] serve {tag}: {done}/{total} shots done")
+        # "batched": the earliest-arrived resident shot and then the shots
+        # with the least remaining work advance, enough of them to give each
+        # launch 12 M cells per step, the others wait resident
+        for name, batched, slots, policy in (("batched", True, 64, "srpt_oldest"),
+                                             ("sequential", False, 1, "all")):
+            torch.cuda.synchronize()
+            sch = Scheduler(TorchDevice(make_inputs, batched=batched), max_slots=slots,
+                            hbm_budget=200 << 30, chunk=25, policy=policy, launch_cells=12 << 20,
+                            progress=progress)
+            o = sch.run(reqs)
+            out[name] = {k: (round(v, 4) if isinstance(v, float) else v)
+                         for k, v in summarize(o, cells.get).items()}
+            out[name]["peak_slots"] = sch.peak_slots
+            log(f"[bench] serve {tag} {name}: {out[name]}")
+        span = reqs[-1].arrival - reqs[0].arrival
+        out["offered_gcell_per_s"] = round(sum(cells[r.rid] for r in reqs) / span / 1e9, 1)
+        out["rate_shots_per_s"] = round((len(reqs) - 1) / span, 2)
+        out["requests"] = len(reqs)
+        return out
+
+    reqs = [Request(r.rid, r.arrival, r.nz, r.nx, r.nt) for r in reqs_in]
+    res = {"rate50": run_pair(reqs, "50/s")}
+    # sub-saturation: the first n_sub shots, seeded exponential gaps at
+    # sub_frac of the rate the batched run sustained (by work, not count)
+    sustained = res["rate50"]["batched"]["gcell_per_s"] * 1e9
+    mean_work = float(np.mean([cells[r.rid] for r in reqs_in[:n_sub]]))
+    rate = sub_frac * sustained / mean_work
+    gaps = np.random.default_rng(seed + 1).exponential(1.0 / rate, n_sub)
+    arr = np.cumsum(gaps)
+    sub = [Request(r.rid, float(t), r.nz, r.nx, r.nt) for r, t in zip(reqs_in[:n_sub], arr)]
+    res["sub"] = run_pair(sub, f"{rate:.1f}/s")
+    res["sub"]["fraction_of_sustained"] = sub_frac
+    res["workload"] = (f"serving streams of 2D shots, 512^2..2048x4096, nt 1000..4000, own seeded GRF model "
+                       f"each: {n_requests} Poisson arrivals at 50/s, and {n_sub} at {sub_frac:.0%} of the "
+                       f"sustained rate")
     return res
 
 
@@ -339,6 +429,49 @@ def cpu_baseline(nsteps: int = 48, threads: int = 0):
                 kind="oracle",
                 sample=f"512^3 layered model, {nsteps} time steps (incl. set-up), FP64, "
                        f"{dt:.1f} s")
+
+
+def oracle_table():
+    """The FP64 oracle's rate on bounded samples of every configuration, on
+    one core and on all the cores this process may use: the 256^2 / 500-step
+    case whole, the 512^3 and 768x768x512 layered models for a few steps
+    (incl. set-up), and one shot of the 1024^2 gradient model forward and
+    forward + adjoint for 200 steps (the adjoint stores every step's
+    Laplacian, nt x 8 MiB); one-core samples are cut to at most 4e8
+    cell-updates.  Mcell-updates/s per sample."""
+    import oracle
+    import fd_inputs as fi
+    allc = int(os.environ.get("OMP_NUM_THREADS", "0")) or len(os.sched_getaffinity(0))
+    rows = []
+    cases = [("[0] 2D 256^2", fi.green2d(), "forward"),
+             ("[1] 3D 512^3", fi.layered3d(nt=6), "forward"),
+             ("[2] 3D 768x768x512", fi.precision3d(nt=4), "forward"),
+             ("[4] 2D 1024^2, one shot", fi.surface2d(1024, 1024, 200, seed=5), "forward"),
+             ("[4] 2D 1024^2, one shot", fi.surface2d(1024, 1024, 200, seed=5), "adjoint")]
+    for name, p, kind in cases:
+        v = p.velocity()
+        g = oracle.grid_of(p)
+        shp = (p.nz, p.ny, p.nx)
+        for threads in (allc, 1):
+            if threads == 1 and p.ncells * p.nt > 4e8:   # one core: about 15 s of work at most
+                p = p.scaled(nt=max(1, int(4e8 // p.ncells)))
+            oracle.set_threads(threads)
+            t = time.perf_counter()
+            if kind == "forward":
+                oracle.forward(g, v.reshape(shp), p.wavelet(), p.nt, p.src, p.rec_index())
+                work = p.ncells * p.nt
+            else:
+                import numpy as np
+                r = np.ones((p.nt, p.receivers.count))
+                oracle.adjoint(g, v.reshape(shp), p.wavelet(), p.nt, p.src, p.rec_index(), r)
+                work = 2 * p.ncells * p.nt   # a forward and an adjoint pass
+            dt = time.perf_counter() - t
+            row = dict(config=name, kind=kind, cells=p.ncells, steps=p.nt, cores=threads,
+                       seconds=round(dt, 2), mcell_per_s=round(work / dt / 1e6, 1))
+            log(f"[bench] oracle {row}")
+            rows.append(row)
+    oracle.set_threads(allc)
+    return rows
 
 
 def slab_leg(nsteps: int = 200, ranks: int = 8):
@@ -461,6 +594,107 @@ def cpu_leg(nsteps: int = 10):
     return out
 
 
+def _csv_rows(root: str, suffix: str):
+    import csv
+    rows = []
+    for d, _, files in os.walk(root):
+        for f in files:
+            if f.endswith(suffix):
+                with open(os.path.join(d, f), newline="") as fh:
+                    rows.extend(csv.DictReader(fh))
+    return rows
+
+
+def summarize_profiles(kt_dir: str, fetch_dir: str, write_dir: str, kernel: str = "k_step3d",
+                       copy_kernel: str = "k_stream", cells: int = 512 ** 3, copy_bytes: int = 1 << 30):
+    """Reads rocprofv3 CSV output (a --kernel-trace --stats run and two --pmc
+    runs, FETCH_SIZE and WRITE_SIZE, of `bench.py --steps 1 --warmup 0
+    --no-cpu --legs none`) and writes the step kernel's summary and traffic
+    record under profiles/.  The byte counters are calibrated on the copy
+    probe's own dispatches (fd_stream_probe kind 0: copy_bytes read and
+    copy_bytes written)."""
+    import hashlib
+    stats = _csv_rows(kt_dir, "kernel_stats.csv")
+    trace = _csv_rows(kt_dir, "kernel_trace.csv")
+    step = [r for r in trace if r.get("Kernel_Name", "").startswith(f"void fdk::{kernel}") or
+            kernel in r.get("Kernel_Name", "").split("<")[0]]
+    durs = sorted((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in step)
+    avg = sum(durs) / len(durs)
+
+    def per_dispatch(rows, name_part, counter):
+        vals = {}
+        for r in rows:
+            if r.get("Counter_Name") == counter and name_part in r.get("Kernel_Name", ""):
+                vals.setdefault(r["Dispatch_Id"], 0.0)
+                vals[r["Dispatch_Id"]] += float(r["Counter_Value"])
+        return list(vals.values())
+
+    fetch_rows = _csv_rows(fetch_dir, "counter_collection.csv")
+    write_rows = _csv_rows(write_dir, "counter_collection.csv")
+    f_step = per_dispatch(fetch_rows, kernel, "FETCH_SIZE")
+    w_step = per_dispatch(write_rows, kernel, "WRITE_SIZE")
+    # the copy probe: kind 0 dispatches only (the kind 1 probe runs on 512^3)
+    f_copy = [v for v in per_dispatch(fetch_rows, copy_kernel + "<0>", "FETCH_SIZE")]
+    w_copy = [v for v in per_dispatch(write_rows, copy_kernel + "<0>", "WRITE_SIZE")]
+    mean = lambda x: sum(x) / len(x)
+    kib = copy_bytes / 1024
+    fscale, wscale = kib / mean(f_copy), kib / mean(w_copy)
+    fetch_kib, write_kib = mean(f_step), mean(w_step)
+    traffic = fetch_kib * 1024 * fscale + write_kib * 1024 * wscale
+    alg = 16.0 * cells
+    src = os.path.join(ROOT, "paper_2311_05038_amd", "csrc")
+    h = hashlib.sha256()
+    for f in sorted(os.listdir(src)):
+        h.update(open(os.path.join(src, f), "rb").read())
+    rec = dict(kernel="k_step3d<f32>", workload="layered3d 512^3, nt=1000", bytes_per_launch=traffic,
+               fetch_kib=fetch_kib, write_kib=write_kib, fetch_scale=fscale, write_scale=wscale,
+               avg_launch_us=avg, launches=len(durs), source_sha256=h.hexdigest())
+    with open(os.path.join(ROOT, "profiles", "k_step3d_f32_layered3d_512_traffic.json"), "w") as fh:
+        json.dump(rec, fh, indent=1)
+    lines = ["| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
+    for r in sorted(stats, key=lambda r: -float(r.get("TotalDurationNs", 0)))[:8]:
+        nm = r["Name"].split("(")[0].replace("void ", "").replace("fdk::", "")
+        nm = nm.split("<")[0] + ("<...>" if "<" in nm else "")
+        lines.append(f"| {nm} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
+                     f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
+                     f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
+    cmd = "python -u bench.py --steps 1 --warmup 0 --no-cpu --legs none"
+    md = f"""# k_step3d<f32> on layered3d 512x512x512 (1 shot, 1000 steps)
+
+Kernel trace:
+
+    cd /tmp && export TMPDIR=/tmp
+    rocprofv3 --kernel-trace --stats -T -f csv -d gpurun_out/prof/kt -o kt -- {cmd}
+
+{chr(10).join(lines)}
+
+Average k_step3d duration {avg:.1f} us over {len(durs)} launches -> {alg / (avg * 1e-6) / 1e9:.1f} GB/s
+algorithmic (16 B per cell-update x {cells:,} cells per launch = {alg / 1e9:.3f} GB),
+i.e. {100 * alg / (avg * 1e-6) / 8e12:.1f}% of the 8 TB/s HBM peak.
+
+Byte counters (one pass each):
+
+    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex "k_step3d|k_stream" -T -f csv -d gpurun_out/prof/fetch -o f -- {cmd}
+    rocprofv3 --pmc WRITE_SIZE --kernel-include-regex "k_step3d|k_stream" -T -f csv -d gpurun_out/prof/write -o w -- {cmd}
+
+| kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | dispatches |
+|---|---|---|---|
+| k_step3d | {fetch_kib:.0f} | {write_kib:.0f} | {len(f_step)} |
+| copy probe (fd_stream_probe kind 0, 1 GiB in + 1 GiB out) | {mean(f_copy):.0f} | {mean(w_copy):.0f} | {len(f_copy)} |
+
+Calibration (the probe moves {kib:,.0f} KiB each way): FETCH_SIZE x {fscale:.3f},
+WRITE_SIZE x {wscale:.3f}.  Scaled traffic per k_step3d launch:
+{fetch_kib * fscale / 1048576:.3f} GiB read + {write_kib * wscale / 1048576:.3f} GiB written
+= {traffic / 1e9:.3f} GB vs {alg / 1e9:.3f} GB algorithmic ({traffic / alg:.3f}x).
+FETCH_SIZE counts L2 misses, including those the Infinity Cache serves.
+
+Summary written by `python bench.py --summarize-profiles gpurun_out/prof/kt gpurun_out/prof/fetch gpurun_out/prof/write`.
+"""
+    with open(os.path.join(ROOT, "profiles", "k_step3d_f32_layered3d_512.md"), "w") as fh:
+        fh.write(md)
+    print(json.dumps(rec))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -469,11 +703,21 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--probe-only", action="store_true",
                     help="only the 1 GiB copy probe (counter calibration)")
-    ap.add_argument("--legs", default="half,adjoint,serve,routines,slab,cpu",
-                    help="comma list of extra legs (half, adjoint, serve, routines, slab, cpu) "
-                         "or 'none'")
-    ap.add_argument("--serve-requests", type=int, default=60)
+    ap.add_argument("--legs", default="half,adjoint,serve,routines,slab,small2d,cpu",
+                    help="comma list of extra legs (half, adjoint, serve, routines, slab, small2d, "
+                         "cpu) or 'none'")
+    ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--summarize-profiles", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
+                    help="write profiles/ summaries from rocprofv3 CSV output (host only)")
+    ap.add_argument("--oracle-table", action="store_true",
+                    help="only the FP64 oracle's rate on samples of every configuration (host only)")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(*args.summarize_profiles)
+        return
+    if args.oracle_table:
+        print(json.dumps({"oracle_table": oracle_table()}), flush=True)
+        return
     if args.gpus != 1:
         print(f"bench.py: this engine runs on one GPU; --gpus {args.gpus} is not supported "
               "(a z-slab steps one device's share; the exchange between devices is not built)",
@@ -487,9 +731,10 @@ def main():
     fd.ensure_built()
 
     probe = copy_probe()
-    log(f"[bench] copy probe: {probe['gbs']:.0f} GB/s")
+    log(f"[bench] copy probe (fd_stream_probe kind 0, 1 GiB each way): {probe['us']:.1f} us, {probe['gbs']:.0f} GB/s")
     sprobe = stream_probe()
-    log(f"[bench] 3-read/1-write stream probe (512^3): {sprobe['us']:.1f} us, {sprobe['gbs']:.0f} GB/s")
+    log(f"[bench] step-pattern stream probe (fd_stream_probe kind 1, 512^3): {sprobe['us']:.1f} us, "
+        f"{sprobe['gbs']:.0f} GB/s")
     if args.probe_only:
         print(json.dumps({"copy_probe": probe}), flush=True)
         return
@@ -506,6 +751,8 @@ def main():
         extra["routines"] = routines_leg()
     if "slab" in legs:
         extra["slab"] = slab_leg()
+    if "small2d" in legs:
+        extra["small2d"] = small2d_leg()
     if "cpu" in legs:
         extra["cpu_backend"] = cpu_leg()
     cpu = cpu1 = None
@@ -523,6 +770,7 @@ def main():
         "steps": args.steps,
         "warmup": args.warmup,
         "ms_per_step": round(h["ms"] / args.steps, 3),
+        "shot_ms": h["shot_ms"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -539,6 +787,7 @@ def main():
         "cpu_baseline_1core": cpu1,
         "copy_roof_gbs": round(probe["gbs"], 1),
         "stream_roof_gbs": round(sprobe["gbs"], 1),
+        "frac_of_stream_roof": round(h["achieved"] / sprobe["gbs"], 4),
     }
     out.update(extra)
     print(json.dumps(out), flush=True)

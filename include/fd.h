@@ -292,6 +292,26 @@ fd_status fd_get_wavefield(const fd_state *state, int32_t which, float *out, voi
  * is first put at rest with next step 0.  No source addition is made. */
 fd_status fd_set_wavefield(fd_state *state, int32_t which, const float *in, void *stream);
 
+/* Health of a shot.  Writes *flags (device, one 4-byte-aligned uint32):
+ * bit 0 set if the state's P holds a non-finite value (NaN or infinity),
+ * bit 1 if its Pold does (on a z-slab: the owned planes), bit 2 if a
+ * non-finite value entered the shot (one of the nt values amp * s[n] the
+ * shot injects, found when fd_begin_shot runs, or a value given to
+ * fd_set_wavefield); 0 for a healthy shot.  Stream-ordered like the steps,
+ * so after fd_run_shot it reports on the finished shot.  With FP32 and
+ * bfloat16 fields a non-finite value never becomes finite again under the
+ * update of Eq. 1 (it, or a non-finite stencil neighbour, makes the new
+ * value non-finite, and the grid's edges and padding hold zeros), so bits 0
+ * and 1 after the last step cover every step, overflow included; binary16
+ * fields decode a non-finite code to a large finite value at the next step,
+ * where bit 2 covers the inputs (their storage scale keeps 16x headroom, so
+ * the scheme itself cannot overflow them).  A shot corrupted this way is
+ * reported here instead of ending with FD_OK and meaningless traces.  Cost:
+ * one read of the two levels (8 bytes per cell with FP32 fields).  Errors:
+ * FD_ERR_INVALID_ARG for NULL or misaligned arguments or a state that has
+ * not begun a shot. */
+fd_status fd_check_finite(const fd_state *state, uint32_t *flags, void *stream);
+
 /* Refreshes the ghost planes between two neighbouring slabs of one grid
  * (see fd_grid: `upper` owns the planes just above `lower`'s, i.e.
  * upper's slab_z0 + nz == lower's slab_z0): the current level P's last 4
@@ -324,18 +344,31 @@ typedef struct {
 fd_status fd_step_batch(fd_batch_item *items, int32_t count, int32_t nsteps, void *stream);
 
 /* Time step n computed as Listing 3 lays it out, one kernel per routine:
- * fd_pzz (the z taps of the second difference of P into a Pzz field),
- * fd_pxx (x taps into Pxx), in 3D the same along y (Pyy), fd_time (Pnew =
- * G (2 P + c (a0 D P + Pzz + Pyy + Pxx)) - G^2 Pold over Pold, receivers
- * sampled into trace_row as in fd_step), add_source (the source addition of
- * step n+1 into Pnew), then the rotation.  The derivative fields live in
- * `work` (device, >= fd_sizes.routines_work bytes, contents undefined on
- * return).  Same preconditions and the same results as fd_step, bit for
- * bit; it moves 40 (2D) or 52 (3D) bytes per cell instead of 16.  It exists
- * to measure the routines one by one against the fused step.  FP32 storage
- * only (FD_ERR_UNSUPPORTED otherwise). */
+ * fd_pzz (the second difference of P along z into a Pzz field), fd_pxx
+ * (along x, into Pxx), in 3D the same along y (Pyy), fd_time (Pnew =
+ * G (2 P + c (Pzz + Pyy + Pxx)) - G^2 Pold over Pold, receivers sampled into
+ * trace_row as in fd_step), add_source (the source addition of step n+1
+ * into Pnew), then the rotation.  The derivative fields live in `work`
+ * (device, >= fd_sizes.routines_work bytes, contents undefined on return).
+ * Same preconditions and the same results as fd_step, bit for bit; it moves
+ * 40 (2D) or 52 (3D) bytes per cell instead of 16.  It exists to measure the
+ * routines one by one against the fused step.  FP32 storage only
+ * (FD_ERR_UNSUPPORTED otherwise). */
 fd_status fd_step_routines(const fd_model *model, fd_state *state, const fd_shot *shot, int64_t n,
                            float *trace_row, void *work, size_t work_bytes, void *stream);
+
+/* The practical memory roof the step kernels are measured against (the
+ * role the measured stream bandwidth plays under the roofline of Section
+ * 7): streams n floats through HBM with no stencil, kind 0 a copy (out = a;
+ * 8 bytes per element) and kind 1 the FP32 step's access pattern (out = a +
+ * b * out: three streams read and one of them rewritten in place; 16 bytes
+ * per element), each in the configuration of its access pattern that
+ * streams fastest on gfx950 (non-temporal stores; non-temporal loads for
+ * kind 1, as in the step kernels).  a, b, out: device, 16-byte
+ * aligned (b unused by kind 0), n a multiple of 4.  Stream-ordered; the
+ * caller times it with events on `stream`.  Errors: FD_ERR_INVALID_ARG for
+ * an unknown kind, NULL or misaligned arrays or n not a multiple of 4. */
+fd_status fd_stream_probe(int32_t kind, const float *a, const float *b, float *out, size_t n, void *stream);
 
 /* Message for the last non-OK status on this thread ("" if none): the error
  * side of the host/device boundary of Section 5 (Start and stop), across

@@ -19,10 +19,11 @@
  *   - built: fd_query_bytes, fd_create_model / fd_destroy_model,
  *     fd_create_state / fd_destroy_state, fd_begin_shot, fd_step,
  *     fd_run_shot (without checkpoints), fd_run_shots, fd_get_wavefield,
- *     fd_set_wavefield, fd_last_error, fd_version - the forward time loop of
- *     Listing 3 (Section 7) in 2D and 3D with FP32 fields, radius 4, zero
- *     edges and the damping band; every other call, 16-bit fields, 16-bit c,
- *     z-slabs and checkpoint buffers return FD_ERR_UNSUPPORTED;
+ *     fd_set_wavefield, fd_check_finite, fd_last_error, fd_version - the
+ *     forward time loop of Listing 3 (Section 7) in 2D and 3D with FP32
+ *     fields, radius 4, zero edges and the damping band; every other call,
+ *     16-bit fields, 16-bit c, z-slabs and checkpoint buffers return
+ *     FD_ERR_UNSUPPORTED;
  *   - the arithmetic is that of the GPU library's FP32 step, operation for
  *     operation (the same fused multiply-adds in the same order), so on the
  *     same inputs both give the same bits; the vector width does not change

@@ -300,6 +300,20 @@ class State:
                               _stream_handle(stream))
         self.next = n + 1
 
+    def check_finite(self, flags: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
+        """Enqueues fd_check_finite: returns a device int32 tensor of one
+        element whose bit 0 (P) and bit 1 (Pold) are set when that level
+        holds a NaN or an infinity (0: the shot is healthy).  Pass `flags`
+        to reuse a buffer."""
+        if flags is None:
+            flags = torch.empty(1, dtype=torch.int32, device=self.model.device)
+        _abi.fd_check_finite(self.handle, flags.data_ptr(), _stream_handle(stream))
+        return flags
+
+    def is_finite(self, stream=None) -> bool:
+        """True when both stored levels are finite (waits for the check)."""
+        return int(self.check_finite(stream=stream).item()) == 0
+
     def wavefield(self, which: int = 0, out: Optional[torch.Tensor] = None,
                   stream=None) -> torch.Tensor:
         if out is None:

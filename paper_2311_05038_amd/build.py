@@ -13,7 +13,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libfd.so")
-SOURCES = ["fd_kernels.hip", "fd_routines.hip", "fd_api.cpp"]
+SOURCES = ["fd_kernels.hip", "fd_routines.hip", "fd_probe.hip", "fd_host.cpp", "fd_api.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 

@@ -168,6 +168,13 @@ class State:
         check(lib().fd_get_wavefield(self.handle, which, out.ctypes.data, None))
         return out
 
+    def check_finite(self) -> int:
+        """fd_check_finite: bit 0 (P) and bit 1 (Pold) set when that level
+        holds a NaN or an infinity; 0 for a healthy shot."""
+        flags = np.zeros(1, dtype=np.uint32)
+        check(lib().fd_check_finite(self.handle, flags.ctypes.data, None))
+        return int(flags[0])
+
     def set_wavefield(self, which: int, values: np.ndarray) -> None:
         v = np.ascontiguousarray(values, dtype=np.float32).reshape(-1)
         if v.size != self.model.grid.ncells:

@@ -4,7 +4,6 @@
 
 #include <algorithm>
 #include <cmath>
-#include <cstdarg>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -12,253 +11,17 @@
 #include <vector>
 
 #include "../../include/fd.h"
+#include "fd_host.hpp"
 #include "fd_launch.hpp"
 
 using fdk::StepArgs;
+using namespace fdh;
 
 namespace {
-
-thread_local std::string g_err;
-
-fd_status fail(fd_status st, const char *fmt, ...)
-{
-    char buf[512];
-    va_list ap;
-    va_start(ap, fmt);
-    vsnprintf(buf, sizeof(buf), fmt, ap);
-    va_end(ap);
-    g_err = buf;
-    return st;
-}
-
-fd_status ok()
-{
-    g_err.clear();
-    return FD_OK;
-}
 
 fd_status hip_fail(hipError_t e, const char *what)
 {
     return fail(FD_ERR_DEVICE, "%s: %s", what, hipGetErrorString(e));
-}
-
-constexpr size_t kAlign = 256;
-size_t align_up(size_t n) { return (n + kAlign - 1) / kAlign * kAlign; }
-
-// Largest magnitude of the 8th-order second-difference symbol, 4096/630.
-constexpr double kSymbolMax = 4096.0 / 630.0;
-constexpr int64_t kMaxDim = (int64_t)1 << 30;
-
-struct Layout {
-    int32_t ndim, storage, c_storage;
-    int64_t nz, ny, nx;
-    int32_t px;        // row pitch in elements (multiple of 64)
-    size_t npad;       // nz * ny * px
-    size_t elem;       // bytes per stored field element
-    size_t field;      // bytes of one stored field, aligned
-    size_t f32field;   // bytes of one FP32 padded field, aligned
-    size_t cfield;     // bytes of the stored c (FP32 or 16-bit fixed point), aligned
-    size_t c_off, gz_off, gy_off, gx_off, scratch_off, model_bytes;
-    size_t state_bytes, meta_off;
-    // z-slab of a larger grid: global index of plane 0, global plane count
-    // (nz for an ordinary grid), and the bytes of the 4 ghost planes that
-    // precede (and follow) a slab's stored level (0 for an ordinary grid)
-    int64_t z0, nzg;
-    size_t ghost;
-};
-
-constexpr int kGhost = 4;  // the stencil radius
-
-bool is_slab(const Layout &L) { return L.nzg != L.nz || L.z0 != 0 || L.ghost != 0; }
-
-Layout make_layout(const fd_grid &g)
-{
-    Layout L{};
-    L.ndim = g.ndim;
-    L.storage = g.storage;
-    L.c_storage = g.c_storage;
-    L.nz = g.nz;
-    L.ny = g.ny;
-    L.nx = g.nx;
-    L.px = (int32_t)((g.nx + 63) / 64 * 64);
-    L.npad = (size_t)g.nz * (size_t)g.ny * (size_t)L.px;
-    L.elem = g.storage == FD_F32 ? 4 : 2;
-    const bool slab = g.slab_nz_global > 0;
-    L.z0 = slab ? g.slab_z0 : 0;
-    L.nzg = slab ? g.slab_nz_global : g.nz;
-    L.ghost = slab ? (size_t)kGhost * (size_t)g.ny * (size_t)L.px * L.elem : 0;
-    L.field = align_up(L.npad * L.elem + 2 * L.ghost);
-    L.f32field = align_up(L.npad * 4);
-    L.cfield = g.c_storage == FD_C_FIXED16 ? align_up(L.npad * 2) : L.f32field;
-    L.c_off = 0;
-    L.gz_off = L.c_off + L.cfield;
-    L.gy_off = L.gz_off + align_up((size_t)g.nz * 4);
-    L.gx_off = L.gy_off + align_up((size_t)g.ny * 4);
-    L.scratch_off = L.gx_off + align_up((size_t)g.nx * 4);
-    L.model_bytes = L.scratch_off + kAlign;
-    L.meta_off = 2 * L.field;
-    L.state_bytes = L.meta_off + align_up(fdk::kMetaWords * 4);
-    return L;
-}
-
-size_t ckpt_slot_bytes(const Layout &L) { return 2 * L.field; }
-
-int64_t n_ckpt(int64_t nt, int32_t every) { return (nt + every - 1) / every; }
-
-size_t adjoint_work_bytes(const Layout &L, int32_t every)
-{
-    // recompute state (2) + history fields (every) + adjoint fields (2) + FP64 sum
-    return 2 * L.f32field + (size_t)every * L.f32field + 2 * L.f32field +
-           align_up(L.npad * 8);
-}
-
-fd_status check_grid(const fd_grid *g)
-{
-    if (!g) return fail(FD_ERR_INVALID_ARG, "grid is NULL");
-    if (g->ndim != 2 && g->ndim != 3) return fail(FD_ERR_INVALID_ARG, "ndim must be 2 or 3 (got %d)", g->ndim);
-    if (g->nz < 1 || g->ny < 1 || g->nx < 1 || g->nz > kMaxDim || g->ny > kMaxDim || g->nx > kMaxDim)
-        return fail(FD_ERR_INVALID_ARG, "grid sizes must be in [1, 2^30] (nz=%lld ny=%lld nx=%lld)",
-                    (long long)g->nz, (long long)g->ny, (long long)g->nx);
-    if (g->ndim == 2 && g->ny != 1) return fail(FD_ERR_INVALID_ARG, "2D grids need ny == 1");
-    if (!(g->dh > 0.0) || !std::isfinite(g->dh)) return fail(FD_ERR_INVALID_ARG, "dh must be > 0");
-    if (!(g->dt > 0.0) || !std::isfinite(g->dt)) return fail(FD_ERR_INVALID_ARG, "dt must be > 0");
-    if (g->radius < 1) return fail(FD_ERR_INVALID_ARG, "radius must be >= 1");
-    if (g->radius != 4) return fail(FD_ERR_UNSUPPORTED, "only radius 4 (8th order) is built");
-    if (g->bc == FD_BC_PERIODIC) return fail(FD_ERR_UNSUPPORTED, "periodic edges are not built");
-    if (g->bc != FD_BC_ZERO) return fail(FD_ERR_INVALID_ARG, "unknown boundary kind %d", g->bc);
-    if (g->sponge_width < 0) return fail(FD_ERR_INVALID_ARG, "sponge_width must be >= 0");
-    if (g->sponge_faces & ~0x3Fu) return fail(FD_ERR_INVALID_ARG, "unknown sponge face bits");
-    if (!std::isfinite(g->sponge_alpha)) return fail(FD_ERR_INVALID_ARG, "sponge_alpha must be finite");
-    if (g->storage != FD_F32 && g->storage != FD_F16 && g->storage != FD_BF16)
-        return fail(FD_ERR_INVALID_ARG, "unknown storage kind %d", g->storage);
-    if (g->c_storage != FD_C_F32 && g->c_storage != FD_C_FIXED16)
-        return fail(FD_ERR_INVALID_ARG, "unknown c storage kind %d", g->c_storage);
-    if (g->c_storage == FD_C_FIXED16 && g->storage == FD_F32)
-        return fail(FD_ERR_UNSUPPORTED, "16-bit c is built for 16-bit fields only");
-    if (g->slab_nz_global < 0 || g->slab_z0 < 0)
-        return fail(FD_ERR_INVALID_ARG, "slab_z0 and slab_nz_global must be >= 0");
-    if (g->slab_nz_global == 0 && g->slab_z0 != 0)
-        return fail(FD_ERR_INVALID_ARG, "slab_z0 needs slab_nz_global > 0");
-    if (g->slab_nz_global > 0) {
-        if (g->ndim != 3) return fail(FD_ERR_UNSUPPORTED, "z-slabs are built for 3D grids");
-        if (g->storage != FD_F32 || g->c_storage != FD_C_F32)
-            return fail(FD_ERR_UNSUPPORTED, "z-slabs are built for FP32 fields and FP32 c");
-        if (g->nz < kGhost) return fail(FD_ERR_INVALID_ARG, "a z-slab needs at least %d planes", kGhost);
-        if (g->slab_nz_global > kMaxDim || g->slab_z0 + g->nz > g->slab_nz_global)
-            return fail(FD_ERR_INVALID_ARG, "slab planes [%lld, %lld) leave the %lld-plane grid",
-                        (long long)g->slab_z0, (long long)(g->slab_z0 + g->nz),
-                        (long long)g->slab_nz_global);
-    }
-    const double cells = (double)(g->nz + 2 * kGhost) * (double)g->ny * (double)((g->nx + 63) / 64 * 64);
-    if (cells > 4.0e9) return fail(FD_ERR_INVALID_ARG, "grid too large");
-    // the 16-bit 3D kernels address a plane with 32-bit byte offsets
-    if ((double)g->ny * (double)((g->nx + 63) / 64 * 64) >= 1073741824.0)
-        return fail(FD_ERR_INVALID_ARG, "an x-y plane must hold fewer than 2^30 cells");
-    return FD_OK;
-}
-
-}  // namespace
-
-struct fd_model {
-    fd_grid grid;
-    Layout L;
-    float *c;          // FP32 c, or null when c is stored in 16-bit fixed point
-    uint16_t *c16;     // 16-bit fixed-point c (value c16 * c16_scale), or null
-    float c16_scale;   // 2^(e - 16)
-    float c16_inv;     // 2^(16 - e)
-    float *gz, *gy, *gx;
-    uint32_t *scratch;
-    float amp;  // dt^2 / h^D
-};
-
-struct fd_state {
-    const fd_model *m;
-    void *base;    // the state buffer
-    void *buf[2];  // plane 0 of each stored level (past a slab's leading ghosts)
-    int32_t *meta;
-    int64_t next;  // next step index, -1 before fd_begin_shot
-};
-
-namespace {
-
-fd_status check_shot(const fd_model *m, const fd_shot *s)
-{
-    if (!s) return fail(FD_ERR_INVALID_ARG, "shot is NULL");
-    const Layout &L = m->L;
-    if (s->nt < 1) return fail(FD_ERR_INVALID_ARG, "shot nt must be >= 1");
-    if (!s->wavelet) return fail(FD_ERR_INVALID_ARG, "shot wavelet is NULL");
-    if (s->src_z < 0 || s->src_z >= L.nzg || s->src_y < 0 || s->src_y >= L.ny || s->src_x < 0 ||
-        s->src_x >= L.nx)
-        return fail(FD_ERR_INVALID_ARG, "source cell (%lld, %lld, %lld) outside the grid",
-                    (long long)s->src_z, (long long)s->src_y, (long long)s->src_x);
-    const fd_receivers &r = s->rec;
-    const int64_t nrec = r.nz * r.ny * r.nx;
-    if (r.nz < 0 || r.ny < 0 || r.nx < 0) return fail(FD_ERR_INVALID_ARG, "negative receiver counts");
-    if (nrec == 0) {
-        if (r.nz || r.ny || r.nx) return fail(FD_ERR_INVALID_ARG, "receiver counts must be all zero or all positive");
-        return FD_OK;
-    }
-    if (nrec > ((int64_t)1 << 30)) return fail(FD_ERR_INVALID_ARG, "too many receivers");
-    if (r.dz < 1 || r.dy < 1 || r.dx < 1) return fail(FD_ERR_INVALID_ARG, "receiver strides must be >= 1");
-    if (r.z0 < 0 || r.y0 < 0 || r.x0 < 0 || r.z0 + (r.nz - 1) * r.dz >= L.nzg ||
-        r.y0 + (r.ny - 1) * r.dy >= L.ny || r.x0 + (r.nx - 1) * r.dx >= L.nx)
-        return fail(FD_ERR_INVALID_ARG, "receiver array leaves the grid");
-    return FD_OK;
-}
-
-int64_t nrec_of(const fd_shot *s) { return s->rec.nz * s->rec.ny * s->rec.nx; }
-
-// Step arguments for a shot.  On a z-slab the global source plane and
-// receiver rows are made local: a source off the slab's planes gets plane
-// -1 (never matched), and only the receiver rows on the slab's planes stay,
-// *rec_skip being the entries of the full trace row that precede them.
-StepArgs base_args(const fd_model *m, const fd_shot *s, int64_t *rec_skip = nullptr)
-{
-    StepArgs a{};
-    const Layout &L = m->L;
-    a.c = m->c;
-    a.c16 = m->c16;
-    a.c16_scale = m->c16_scale;
-    a.c16_inv = m->c16_inv;
-    a.gz = m->gz;
-    a.gy = m->gy;
-    a.gx = m->gx;
-    a.nz = (int32_t)L.nz;
-    a.ny = (int32_t)L.ny;
-    a.nx = (int32_t)L.nx;
-    a.px = L.px;
-    a.amp = m->amp;
-    if (s) {
-        const int64_t lz = s->src_z - L.z0;
-        a.sz = (lz >= 0 && lz < L.nz) ? (int32_t)lz : -1;
-        a.sy = (int32_t)s->src_y;
-        a.sx = (int32_t)s->src_x;
-        a.wavelet = s->wavelet;
-        a.nt = s->nt;
-        const fd_receivers &r = s->rec;
-        // receiver rows i in [i0, i1) lie on planes [z0, z0 + nz)
-        int64_t i0 = 0, i1 = r.nz;
-        if (nrec_of(s) > 0 && is_slab(L)) {
-            i0 = std::max<int64_t>(0, (L.z0 - r.z0 + r.dz - 1) / r.dz);
-            const int64_t zl = L.z0 + L.nz - 1 - r.z0;  // the slab's last plane, from row 0
-            i1 = zl < 0 ? 0 : std::min<int64_t>(r.nz, zl / r.dz + 1);
-        }
-        if (nrec_of(s) > 0 && i1 > i0) {
-            a.rec = fdk::RecBox{(int32_t)(r.z0 + i0 * r.dz - L.z0), (int32_t)r.y0, (int32_t)r.x0,
-                                (int32_t)(i1 - i0), (int32_t)r.ny, (int32_t)r.nx, (int32_t)r.dz,
-                                (int32_t)r.dy, (int32_t)r.dx};
-            if (rec_skip) *rec_skip = i0 * r.ny * r.nx;
-        } else {
-            a.rec = fdk::RecBox{0, 0, 0, 0, 0, 0, 1, 1, 1};
-            if (rec_skip) *rec_skip = -1;
-        }
-    }
-    return a;
-}
-
-size_t src_offset(const Layout &L, const fd_shot *s)
-{
-    return ((size_t)s->src_z * (size_t)L.ny + (size_t)s->src_y) * (size_t)L.px + (size_t)s->src_x;
 }
 
 fd_status do_begin(const fd_model *m, fd_state *st, const fd_shot *s, hipStream_t stream)
@@ -271,7 +34,7 @@ fd_status do_begin(const fd_model *m, fd_state *st, const fd_shot *s, hipStream_
         fd_shot local = *s;
         local.src_z -= L.z0;
         e = fdk::launch_begin(L.storage, st->buf[0], (int64_t)src_offset(L, &local), m->amp,
-                              s->wavelet, st->meta, stream);
+                              s->wavelet, s->nt, st->meta, stream);
         if (e != hipSuccess) return hip_fail(e, "fd_begin_shot");
     }
     st->next = 0;
@@ -299,7 +62,7 @@ fd_status do_step(const fd_model *m, fd_state *st, const fd_shot *s, int64_t n, 
 
 extern "C" {
 
-const char *fd_last_error(void) { return g_err.c_str(); }
+const char *fd_last_error(void) { return last_error(); }
 
 const char *fd_version(void) { return "fd-mi355x 0.1 (gfx950, radius 4)"; }
 
@@ -346,30 +109,18 @@ fd_status fd_create_model(const fd_grid *grid, const float *velocity, void *mode
     m->gy = (float *)(base + L.gy_off);
     m->gx = (float *)(base + L.gx_off);
     m->scratch = (uint32_t *)(base + L.scratch_off);
-    m->amp = (float)(grid->dt * grid->dt / std::pow(grid->dh, (double)grid->ndim));
+    m->amp = source_amp(*grid);
 
-    // Damping profiles g(i) = exp(-(alpha d)^2), FP64 on the host, stored FP32.
+    // Damping profiles, FP64 on the host, stored FP32; a z-slab takes its
+    // planes' factors from the whole grid's profile.
     const double alpha = m->grid.sponge_alpha;
     const int32_t W = m->grid.sponge_width;
     const uint32_t f = m->grid.sponge_faces;
-    auto profile = [&](int64_t n, bool lo, bool hi) {
-        std::vector<float> g((size_t)n);
-        for (int64_t i = 0; i < n; ++i) {
-            double d = 0.0;
-            if (W > 0) {
-                if (lo && (double)(W - i) > d) d = (double)(W - i);
-                if (hi && (double)(i - (n - 1 - W)) > d) d = (double)(i - (n - 1 - W));
-            }
-            g[(size_t)i] = (float)std::exp(-(alpha * d) * (alpha * d));
-        }
-        return g;
-    };
-    // a z-slab takes its planes' factors from the whole grid's profile
-    const std::vector<float> gzg = profile(L.nzg, f & FD_FACE_ZLO, f & FD_FACE_ZHI);
+    const std::vector<float> gzg = damping_profile(L.nzg, W, alpha, f & FD_FACE_ZLO, f & FD_FACE_ZHI);
     const std::vector<float> gz(gzg.begin() + L.z0, gzg.begin() + L.z0 + L.nz);
-    const std::vector<float> gy = grid->ndim == 3 ? profile(L.ny, f & FD_FACE_YLO, f & FD_FACE_YHI)
+    const std::vector<float> gy = grid->ndim == 3 ? damping_profile(L.ny, W, alpha, f & FD_FACE_YLO, f & FD_FACE_YHI)
                                                   : std::vector<float>(1, 1.0f);
-    const std::vector<float> gx = profile(L.nx, f & FD_FACE_XLO, f & FD_FACE_XHI);
+    const std::vector<float> gx = damping_profile(L.nx, W, alpha, f & FD_FACE_XLO, f & FD_FACE_XHI);
 
     hipStream_t s = (hipStream_t)stream;
     uint32_t host_scratch[2] = {0, 0};
@@ -395,24 +146,13 @@ fd_status fd_create_model(const fd_grid *grid, const float *velocity, void *mode
     }
     float vmax;
     std::memcpy(&vmax, &host_scratch[0], 4);
-    const double cfl = (double)vmax * grid->dt / grid->dh;
-    const double lhs = cfl * cfl * grid->ndim * kSymbolMax;
-    if (!(lhs <= 4.0)) {
+    st = check_stability(*grid, vmax);
+    if (st != FD_OK) {
         delete m;
-        return fail(FD_ERR_UNSTABLE,
-                    "unstable: vmax*dt/dh = %.6f exceeds the %dD limit %.6f", cfl, grid->ndim,
-                    std::sqrt(4.0 / (grid->ndim * kSymbolMax)));
+        return st;
     }
     if (fixed16) {
-        // the largest c, rounded to FP32 exactly as the kernels round every c
-        // (the product is monotone in v), fixes e = floor(log2 cmax) + 1
-        const double qq = (double)vmax * (grid->dt / grid->dh);
-        const float cmax = (float)(qq * qq);
-        int ex = 0;
-        std::frexp(cmax, &ex);  // cmax = f 2^ex with f in [0.5, 1)
-        // a cmax within half a code of 2^ex would round to code 2^16: the
-        // next binade keeps every code in 16 bits and the error <= 2^(e-17)
-        if (std::nearbyint(std::ldexp((double)cmax, 16 - ex)) > 65535.0) ex += 1;
+        const int ex = c16_exponent(vmax, grid->dt / grid->dh);
         m->c16_scale = std::ldexp(1.0f, ex - 16);
         m->c16_inv = std::ldexp(1.0f, 16 - ex);
         e = fdk::launch_model_c16(velocity, m->c16, L.nz * L.ny, (int32_t)L.nx, L.px,
@@ -854,6 +594,37 @@ fd_status fd_set_wavefield(fd_state *state, int32_t which, const float *in, void
     hipError_t e = fdk::launch_set_field(L.storage, in, state->buf[lvl & 1], L.nz * L.ny,
                                          (int32_t)L.nx, L.px, state->meta, (int32_t)(lvl & 3), s);
     if (e != hipSuccess) return hip_fail(e, "fd_set_wavefield");
+    return ok();
+}
+
+fd_status fd_check_finite(const fd_state *state, uint32_t *flags, void *stream)
+{
+    if (!state || !flags) return fail(FD_ERR_INVALID_ARG, "NULL state or flags");
+    if ((uintptr_t)flags % 4) return fail(FD_ERR_INVALID_ARG, "flags must be 4-byte aligned");
+    if (state->next < 0) return fail(FD_ERR_INVALID_ARG, "fd_begin_shot has not been called");
+    const Layout &L = state->m->L;
+    hipStream_t s = (hipStream_t)stream;
+    // the owned cells of each level (padding included: it holds zeros)
+    const size_t bytes = L.npad * L.elem;
+    hipError_t e = fdk::launch_fill_u32(flags, 1, 0u, s);
+    if (e == hipSuccess)
+        e = fdk::launch_nonfinite(L.storage, state->buf[state->next & 1], bytes, flags, 1u,
+                                  state->meta + fdk::kHealth, s);
+    if (e == hipSuccess)
+        e = fdk::launch_nonfinite(L.storage, state->buf[(state->next + 1) & 1], bytes, flags, 2u, nullptr, s);
+    if (e != hipSuccess) return hip_fail(e, "fd_check_finite");
+    return ok();
+}
+
+fd_status fd_stream_probe(int32_t kind, const float *a, const float *b, float *out, size_t n, void *stream)
+{
+    if (kind != 0 && kind != 1) return fail(FD_ERR_INVALID_ARG, "kind must be 0 (copy) or 1 (out = a + b * out)");
+    if (!a || !out || (kind == 1 && !b)) return fail(FD_ERR_INVALID_ARG, "NULL array");
+    if (n % 4) return fail(FD_ERR_INVALID_ARG, "n must be a multiple of 4");
+    if ((uintptr_t)a % 16 || (uintptr_t)out % 16 || (kind == 1 && (uintptr_t)b % 16))
+        return fail(FD_ERR_INVALID_ARG, "arrays must be 16-byte aligned");
+    const hipError_t e = fdk::launch_stream_probe(kind, a, b, out, n, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "fd_stream_probe");
     return ok();
 }
 

@@ -12,6 +12,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "fd_args.hpp"
+
 namespace fdk {
 
 // 8th-order central second-difference weights (radius 4), h = 1.
@@ -31,18 +33,23 @@ __device__ __forceinline__ float stencil_taps(float m4, float m3, float m2, floa
 }
 
 // The whole second difference along one axis, a_0 u + sum_k a_k (u_{-k} +
-// u_{+k}), evaluated as sum_k a_k ((u_{-k} - u) + (u_{+k} - u)) (equal, since
-// a_0 = -2 sum_k a_k).  For a smooth field the differences are small and
-// nearly exact, so the rounding error is relative to the derivative rather
-// than to u itself; summing a_0 u with the taps instead cancels ~6.5 |u| down
-// to the derivative, and that error, carried by the leapfrog's slowly
-// decaying long-wavelength modes, dominated the FP32 field error (about ten
-// times the difference form's over a few hundred steps).
+// u_{+k}), evaluated with the two large weights on differences from the
+// centre value:
+//   a_1 ((u_{-1} - u) + (u_{+1} - u)) + a_2 ((u_{-2} - u) + (u_{+2} - u))
+//     + a_3 (u_{-3} + u_{+3}) + a_4 (u_{-4} + u_{+4}) - 2 (a_3 + a_4) u
+// (equal, since a_0 = -2 (a_1 + a_2 + a_3 + a_4); -2 (a_3 + a_4) = -17/360).
+// For a smooth field the differences are small and nearly exact, so the
+// partial sums stay near the derivative (within 0.05 |u|) instead of reaching
+// a_1 2 |u| = 3.2 |u| as when a_0 u is summed against all the taps; that
+// cancellation error, carried by the leapfrog's slowly decaying
+// long-wavelength modes, dominated the FP32 field error.  Differences on all
+// four taps give the same accuracy at three more instructions per axis.
+constexpr float kC34 = (float)(-17.0 / 360.0);
 __device__ __forceinline__ float axis_d2(float m4, float m3, float m2, float m1, float u, float p1,
                                          float p2, float p3, float p4)
 {
-    return fmaf(kA4, (m4 - u) + (p4 - u),
-                fmaf(kA3, (m3 - u) + (p3 - u), fmaf(kA2, (m2 - u) + (p2 - u), kA1 * ((m1 - u) + (p1 - u)))));
+    return fmaf(kC34, u,
+                fmaf(kA4, m4 + p4, fmaf(kA3, m3 + p3, fmaf(kA2, (m2 - u) + (p2 - u), kA1 * ((m1 - u) + (p1 - u))))));
 }
 
 // new = G (2 cur + c lap) - G^2 prev, evaluated as G (cur + (c lap + (cur -
@@ -52,62 +59,6 @@ __device__ __forceinline__ float leapfrog(float G, float ctr, float c, float lap
 {
     return G * (ctr + fmaf(c, lap, fmaf(-G, prev, ctr)));
 }
-
-enum Mode : int {
-    kFwd = 0,     // forward step
-    kFwdLap = 1,  // forward step that also stores L(cur) (gradient recompute)
-    kAdj = 2      // adjoint step: receiver injection of c G r, g += new * hist
-};
-
-// Forward modes that write a per-step history field (StepArgs::lap).
-constexpr bool stores_history(int mode) { return mode == kFwdLap; }
-
-enum StorageKind : int { kF32 = 0, kF16 = 1, kBF16 = 2 };
-
-struct RecBox {
-    int32_t z0, y0, x0;
-    int32_t nz, ny, nx;
-    int32_t dz, dy, dx;
-};
-
-// Arguments of one step on one grid.  Field buffers use a padded layout:
-// element (z, y, x) sits at (z * ny + y) * px + x with px a multiple of 64;
-// cells with x >= nx are zero in every field.
-struct StepArgs {
-    const void *cur;      // level n
-    void *prev;           // level n-1 in, level n+1 out (unless `out` is set)
-    void *out;            // forward steps: level n+1 here instead, prev only read
-    const float *c;       // (v dt / h)^2, padded, zero in padding (FP32 c)
-    const uint16_t *c16;  // or 16-bit fixed point: c = c16 * c16_scale (else null)
-    float c16_scale;      // 2^(e - 16)
-    float c16_inv;        // 2^(16 - e)
-    const float *gz, *gy, *gx;  // damping profiles (nz, ny, nx entries)
-    int32_t nz, ny, nx, px;
-    int32_t zc;           // planes (rows in 2D) per block
-    int16_t vx;           // cells per lane along x (2D tile width 64 * vx)
-    int16_t zghost;       // 3D FP32: planes of cur readable past each z end (the
-                          // ghost planes of a z-slab), else 0 (zero edges)
-    int32_t tiles_x, tiles_y, tiles_z;
-    int32_t resident;     // 3D: blocks resident at once (tile mapping)
-    int32_t sz, sy, sx;   // source cell
-    float amp;            // dt^2 / h^D
-    const float *wavelet; // device, nt samples
-    int64_t n, nt;
-    RecBox rec;
-    int32_t gmode;        // (fills the padding after rec)
-                          // kAdj: 0 g += new lap; 1 no g update (deferred to a later
-                          // step); 2 g += cur lap2, then new lap; 3 g += prev lap3,
-                          // then cur lap2, then new lap (the deferred terms first:
-                          // descending level order)
-    float *trace_row;     // nrec floats of row n, or null
-    int32_t *meta;        // 16-bit storage: e[4] exponents then max|.|[4] bits
-    float *lap;           // kFwdLap: out (L cur);  kAdj: in (history of level k-1),
-                          // padded FP32
-    const float *lap2;    // kAdj, gmode 2 and 3: history of level k
-    const float *lap3;    // kAdj, gmode 3: history of level k+1
-    const float *resid_row;  // kAdj: dJ/dtraces row k-1 (nrec), or null
-    double *g;            // kAdj: FP64 accumulator, padded
-};
 
 template <int ST> struct Stor { using T = uint16_t; };
 template <> struct Stor<kF32> { using T = float; };
@@ -273,15 +224,6 @@ struct HalfCtx {
     float sn;       // 2^en: storage units -> value (traces, magnitude)
     float sn_inv;   // 2^-en: value -> storage units (source term)
 };
-
-// Layout of the 16-bit storage bookkeeping ("meta", in the state buffer):
-// meta[l] (l < 4) is the exponent of time level l mod 4; the largest
-// magnitude of level l is the maximum over kMaxSlots words at
-// meta[kMaxBase + l * kMaxSlots + k] (float bit patterns; blocks fold their
-// maxima into slot blockIdx % kMaxSlots, which spreads the atomics).
-constexpr int kMaxSlots = 64;
-constexpr int kMaxBase = 16;
-constexpr int kMetaWords = kMaxBase + 4 * kMaxSlots;
 
 __device__ __forceinline__ float level_max(const int32_t *meta, int level)
 {

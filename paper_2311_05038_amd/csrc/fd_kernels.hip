@@ -717,11 +717,16 @@ __global__ void k_model_c16(const float *__restrict__ v, uint16_t *__restrict__ 
 }
 
 // First source addition of a shot into the zeroed level-0 field (+ the
-// storage exponent and magnitude of levels 0 and -1).
+// storage exponent and magnitude of levels 0 and -1).  The wave also scans
+// the shot's nt injected values amp * s[n] and records a non-finite one in
+// the shot's health flags.
 template <int ST>
-__global__ void k_begin(void *cur, int64_t src_off, float amp, const float *wavelet,
+__global__ void k_begin(void *cur, int64_t src_off, float amp, const float *wavelet, int64_t nt,
                         int32_t *meta)
 {
+    bool bad = false;
+    for (int64_t i = threadIdx.x; i < nt; i += blockDim.x) bad |= !(fabsf(amp * wavelet[i]) <= 3.4028235e38f);
+    if (__ballot(bad) != 0 && threadIdx.x == 0) atomicOr((uint32_t *)&meta[kHealth], kNonfiniteInput);
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     using T = typename Stor<ST>::T;
     const float x0 = amp * wavelet[0];
@@ -781,11 +786,46 @@ __global__ void k_set_field(const float *__restrict__ in, void *buf, int64_t nro
     const size_t total = (size_t)nrows * px;
     size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
     const size_t stride = (size_t)gridDim.x * blockDim.x;
+    bool bad = false;
     for (; i < total; i += stride) {
         const size_t rw = i / (size_t)px, x = i - rw * (size_t)px;
         const float v = x < (size_t)nx ? in[rw * (size_t)nx + x] : 0.0f;
+        bad |= !(fabsf(v) <= 3.4028235e38f);
         ((T *)buf)[i] = encode<ST>(v, inv);
     }
+    // a non-finite value set into the shot is recorded in its health flags
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr((uint32_t *)&meta[kHealth], kNonfiniteInput);
+}
+
+// Sets `bit` in *flags when a stored level holds a non-finite value (NaN or
+// infinity), and (health non-null) the shot's sticky non-finite-input flag: the exponent field of a code all ones (FP32 0x7F800000,
+// binary16 0x7C00, bfloat16 0x7F80), tested on the raw codes 16 bytes at a
+// time without decoding; one atomic per wave that found one.
+template <int ST>
+__global__ void k_nonfinite(const uint4 *__restrict__ p, size_t n16, uint32_t *flags, uint32_t bit,
+                            const int32_t *health)
+{
+    if (health != nullptr && blockIdx.x == 0 && threadIdx.x == 0) {
+        const uint32_t hf = (uint32_t)*health & kNonfiniteInput;
+        if (hf) atomicOr(flags, hf);
+    }
+    bool bad = false;
+    size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const size_t stride = (size_t)gridDim.x * blockDim.x;
+    for (; i < n16; i += stride) {
+        const uint4 q = p[i];
+        const uint32_t w[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            if constexpr (ST == kF32)
+                bad |= (w[k] & 0x7F800000u) == 0x7F800000u;
+            else if constexpr (ST == kF16)
+                bad |= ((w[k] & 0x7C00u) == 0x7C00u) | ((w[k] & 0x7C000000u) == 0x7C000000u);
+            else
+                bad |= ((w[k] & 0x7F80u) == 0x7F80u) | ((w[k] & 0x7F800000u) == 0x7F800000u);
+        }
+    }
+    if (__ballot(bad) != 0 && (threadIdx.x & 63) == 0) atomicOr(flags, bit);
 }
 
 // grad_v += dJ/dc * 2c/v with v = (h/dt) sqrt(c): 2 g dt / (h sqrt(c)).
@@ -852,12 +892,12 @@ hipError_t launch_model_c16(const float *v, uint16_t *c16, int64_t nrows, int32_
 }
 
 hipError_t launch_begin(int storage, void *cur, int64_t src_off, float amp,
-                        const float *wavelet, int32_t *meta, hipStream_t s)
+                        const float *wavelet, int64_t nt, int32_t *meta, hipStream_t s)
 {
     switch (storage) {
-    case kF32: hipLaunchKernelGGL(k_begin<kF32>, dim3(1), dim3(64), 0, s, cur, src_off, amp, wavelet, meta); break;
-    case kF16: hipLaunchKernelGGL(k_begin<kF16>, dim3(1), dim3(64), 0, s, cur, src_off, amp, wavelet, meta); break;
-    default: hipLaunchKernelGGL(k_begin<kBF16>, dim3(1), dim3(64), 0, s, cur, src_off, amp, wavelet, meta); break;
+    case kF32: hipLaunchKernelGGL(k_begin<kF32>, dim3(1), dim3(64), 0, s, cur, src_off, amp, wavelet, nt, meta); break;
+    case kF16: hipLaunchKernelGGL(k_begin<kF16>, dim3(1), dim3(64), 0, s, cur, src_off, amp, wavelet, nt, meta); break;
+    default: hipLaunchKernelGGL(k_begin<kBF16>, dim3(1), dim3(64), 0, s, cur, src_off, amp, wavelet, nt, meta); break;
     }
     return hipGetLastError();
 }
@@ -891,6 +931,22 @@ hipError_t launch_set_field(int storage, const float *in, void *buf, int64_t nro
     case kF32: hipLaunchKernelGGL(k_set_field<kF32>, g, b, 0, s, in, buf, nrows, nx, px, meta, slot); break;
     case kF16: hipLaunchKernelGGL(k_set_field<kF16>, g, b, 0, s, in, buf, nrows, nx, px, meta, slot); break;
     default: hipLaunchKernelGGL(k_set_field<kBF16>, g, b, 0, s, in, buf, nrows, nx, px, meta, slot); break;
+    }
+    return hipGetLastError();
+}
+
+hipError_t launch_nonfinite(int storage, const void *level, size_t bytes, uint32_t *flags, uint32_t bit,
+                            const int32_t *health, hipStream_t s)
+{
+    if (bytes % 16 != 0) return hipErrorInvalidValue;
+    const size_t n16 = bytes / 16;
+    if (n16 == 0) return hipSuccess;
+    const dim3 g(grid_blocks(n16, 256)), b(256);
+    const uint4 *p = (const uint4 *)level;
+    switch (storage) {
+    case kF32: hipLaunchKernelGGL(k_nonfinite<kF32>, g, b, 0, s, p, n16, flags, bit, health); break;
+    case kF16: hipLaunchKernelGGL(k_nonfinite<kF16>, g, b, 0, s, p, n16, flags, bit, health); break;
+    default: hipLaunchKernelGGL(k_nonfinite<kBF16>, g, b, 0, s, p, n16, flags, bit, health); break;
     }
     return hipGetLastError();
 }

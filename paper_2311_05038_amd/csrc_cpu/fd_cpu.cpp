@@ -212,6 +212,7 @@ struct fd_state {
     const fd_model *m;
     float *buf[2];  // the two stored levels
     int64_t next;   // next step, -1 before fd_begin_shot
+    uint32_t health;  // bit 2: a non-finite value entered the shot (as in fd.h)
 };
 
 namespace {
@@ -235,8 +236,12 @@ fd_status check_shot(const fd_model *m, const fd_shot *s)
     if ((double)r.nz * (double)r.ny * (double)r.nx > (double)((int64_t)1 << 30))
         return fail(FD_ERR_INVALID_ARG, "too many receivers");
     if (r.dz < 1 || r.dy < 1 || r.dx < 1) return fail(FD_ERR_INVALID_ARG, "receiver strides must be >= 1");
-    if (r.z0 < 0 || r.y0 < 0 || r.x0 < 0 || r.z0 + (r.nz - 1) * r.dz >= L.nz ||
-        r.y0 + (r.ny - 1) * r.dy >= L.ny || r.x0 + (r.nx - 1) * r.dx >= L.nx)
+    // the array's last cell along an axis of n cells, tested by division (no
+    // overflow for any int64 input): x0 + (cnt - 1) d <= n - 1
+    auto inside = [](int64_t x0, int64_t cnt, int64_t d, int64_t n) {
+        return x0 >= 0 && x0 < n && (cnt - 1) <= (n - 1 - x0) / d;
+    };
+    if (!inside(r.z0, r.nz, r.dz, L.nz) || !inside(r.y0, r.ny, r.dy, L.ny) || !inside(r.x0, r.nx, r.dx, L.nx))
         return fail(FD_ERR_INVALID_ARG, "receiver array leaves the grid");
     return FD_OK;
 }
@@ -343,6 +348,10 @@ void do_begin(const fd_model *m, fd_state *st, const fd_shot *s)
         for (int lvl = 0; lvl < 2; ++lvl)
             std::memset(st->buf[lvl] + (size_t)p * L.zs, 0, (size_t)L.zs * 4);
     if (s) st->buf[0][index_of(L, s->src_z, s->src_y, s->src_x)] = m->amp * s->wavelet[0];
+    st->health = 0;
+    if (s)
+        for (int64_t n = 0; n < s->nt; ++n)
+            if (!std::isfinite(m->amp * s->wavelet[n])) st->health |= 4u;
     st->next = 0;
 }
 
@@ -547,6 +556,7 @@ fd_status fd_create_state(const fd_model *model, void *state_buf, size_t state_b
     st->buf[0] = (float *)state_buf;
     st->buf[1] = (float *)((char *)state_buf + model->L.field);
     st->next = -1;
+    st->health = 0;
     *out = st;
     return ok();
 }
@@ -662,11 +672,39 @@ fd_status fd_set_wavefield(fd_state *state, int32_t which, const float *in, void
     const int64_t lvl = which == 0 ? state->next : state->next - 1;
     float *buf = state->buf[lvl & 1];
     const int32_t T = threads();
-#pragma omp parallel for schedule(static) num_threads(T)
+    int bad = 0;
+#pragma omp parallel for schedule(static) num_threads(T) reduction(| : bad)
     for (int64_t z = 0; z < L.nz; ++z)
-        for (int64_t y = 0; y < L.ny; ++y)
-            std::memcpy(buf + index_of(L, z, y, 0), in + (size_t)(z * L.ny + y) * (size_t)L.nx,
-                        (size_t)L.nx * 4);
+        for (int64_t y = 0; y < L.ny; ++y) {
+            const float *src = in + (size_t)(z * L.ny + y) * (size_t)L.nx;
+            std::memcpy(buf + index_of(L, z, y, 0), src, (size_t)L.nx * 4);
+            for (int64_t x = 0; x < L.nx; ++x) bad |= !std::isfinite(src[x]);
+        }
+    if (bad) state->health |= 4u;
+    return ok();
+}
+
+fd_status fd_check_finite(const fd_state *state, uint32_t *flags, void *stream)
+{
+    (void)stream;
+    if (!state || !flags) return fail(FD_ERR_INVALID_ARG, "NULL state or flags");
+    if ((uintptr_t)flags % 4) return fail(FD_ERR_INVALID_ARG, "flags must be 4-byte aligned");
+    if (state->next < 0) return fail(FD_ERR_INVALID_ARG, "fd_begin_shot has not been called");
+    const Layout &L = state->m->L;
+    uint32_t f = 0;
+    for (int lvl = 0; lvl < 2; ++lvl) {
+        const float *buf = state->buf[(state->next + lvl) & 1];
+        int bad = 0;
+        const int32_t T = threads();
+#pragma omp parallel for schedule(static) num_threads(T) reduction(| : bad)
+        for (int64_t z = 0; z < L.nz; ++z)
+            for (int64_t y = 0; y < L.ny; ++y) {
+                const float *row = buf + index_of(L, z, y, 0);
+                for (int64_t x = 0; x < L.nx; ++x) bad |= !std::isfinite(row[x]);
+            }
+        if (bad) f |= 1u << lvl;
+    }
+    *flags = f | (state->health & 4u);
     return ok();
 }
 
@@ -711,6 +749,11 @@ fd_status fd_step_routines(const fd_model *, fd_state *, const fd_shot *, int64_
                            size_t, void *)
 {
     return unsupported("fd_step_routines");
+}
+
+fd_status fd_stream_probe(int32_t, const float *, const float *, float *, size_t, void *)
+{
+    return unsupported("fd_stream_probe (the host roof is fd_cpu_stream_probe)");
 }
 
 }  // extern "C"

@@ -9,8 +9,9 @@
 // a = (-205/72, 8/5, -1/5, 8/315, -1/560)).  Every multiply-add is an exact
 // fused one and the order of operations is fixed, so the result does not
 // depend on the vector width: each axis as
-// a4 d4 + (a3 d3 + (a2 d2 + a1 d1)) with dk = (u-k - u) + (u+k - u) (the
-// centre weight a0 = -2 (a1 + a2 + a3 + a4) folded into the differences),
+// c34 u + (a4 s4 + (a3 s3 + (a2 d2 + a1 d1))) with dk = (u-k - u) + (u+k - u),
+// sk = u-k + u+k and c34 = -2 (a3 + a4) = -17/360 (the centre weight
+// a0 = -2 (a1 + a2 + a3 + a4) folded into the two differences and c34),
 // axes as z + (y + x), and the update as G (P + (c L + (P - G Pold))).
 #pragma once
 
@@ -23,6 +24,7 @@ constexpr float kA1 = (float)(8.0 / 5.0);
 constexpr float kA2 = (float)(-1.0 / 5.0);
 constexpr float kA3 = (float)(8.0 / 315.0);
 constexpr float kA4 = (float)(-1.0 / 560.0);
+constexpr float kC34 = (float)(-17.0 / 360.0);
 
 // One row's pointers.  P points at cell (z, y, x = 0) of the current level;
 // neighbours at +-k along x are P[x +- k], along y P[x +- k*ys] and along z
@@ -51,8 +53,9 @@ inline typename O::V axis_d2(const float *p, ptrdiff_t s, typename O::V u)
     using V = typename O::V;
     const V t1 = O::mul(O::set1(kA1), dsum<O>(O::ld(p - s), u, O::ld(p + s)));
     const V t2 = O::fma(O::set1(kA2), dsum<O>(O::ld(p - 2 * s), u, O::ld(p + 2 * s)), t1);
-    const V t3 = O::fma(O::set1(kA3), dsum<O>(O::ld(p - 3 * s), u, O::ld(p + 3 * s)), t2);
-    return O::fma(O::set1(kA4), dsum<O>(O::ld(p - 4 * s), u, O::ld(p + 4 * s)), t3);
+    const V t3 = O::fma(O::set1(kA3), O::add(O::ld(p - 3 * s), O::ld(p + 3 * s)), t2);
+    const V t4 = O::fma(O::set1(kA4), O::add(O::ld(p - 4 * s), O::ld(p + 4 * s)), t3);
+    return O::fma(O::set1(kC34), u, t4);
 }
 
 template <class O, int NDIM>

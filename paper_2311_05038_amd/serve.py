@@ -11,8 +11,10 @@ passed that step.  Latency = completion - arrival.
 
 The scheduling core (`Scheduler`) is device-agnostic: it drives any object
 with the methods of `TorchDevice` (footprint, start, advance, fence, done,
-wait, elapsed, finish), which lets the policy be tested on the CPU against a
-simulated device.
+wait, elapsed, finish, and optionally health), which lets the policy be
+tested on the CPU against a simulated device.  A shot whose wavefield ends
+non-finite (NaN or infinity: a corrupted input or an overflow) fails alone:
+its outcome says so and the other shots of the mix are unaffected.
 """
 from __future__ import annotations
 
@@ -72,7 +74,8 @@ class Scheduler:
 
     def __init__(self, device, max_slots: int = 64, hbm_budget: int = 64 << 30,
                  chunk: int = 25, depth: int = 2, policy: str = "srpt_oldest",
-                 launch_cells: int = 12 << 20, launch_max: int = 16):
+                 launch_cells: int = 12 << 20, launch_max: int = 16,
+                 progress: Optional[Callable[[int, int], None]] = None):
         if policy not in ("all", "srpt", "srpt_oldest"):
             raise ValueError(f"unknown policy {policy!r}")
         self.dev = device
@@ -83,6 +86,7 @@ class Scheduler:
         self.policy = policy
         self.launch_cells = launch_cells
         self.launch_max = launch_max
+        self.progress = progress        # called as progress(finished, total) when shots retire
         self.peak_bytes = 0
         self.peak_slots = 0
         self.launch_steps = 0
@@ -117,6 +121,7 @@ class Scheduler:
         inflight: collections.deque = collections.deque()  # (token, [handles done])
         used = 0
         out = {r.rid: Outcome(r.rid, r.arrival) for r in requests}
+        n_done = 0
         dev.begin_stream()
         while pending or waiting or active or inflight:
             now = dev.elapsed()
@@ -168,9 +173,13 @@ class Scheduler:
                     stepped.pop(id(h), None)
                     o = out[req.rid]
                     o.finished = t_done
-                    o.status = "ok"
+                    err = dev.health(h) if hasattr(dev, "health") else None
+                    o.status = "ok" if err is None else f"failed: {err}"
                     o.result = dev.finish(h)
                     used -= dev.footprint(req)
+                    n_done += 1
+                if finished and self.progress is not None:
+                    self.progress(n_done, len(requests))
                 if not active and waiting:
                     break   # go back and admit
             if not active and not inflight and not waiting and pending:
@@ -190,7 +199,8 @@ def summarize(outcomes: Dict[int, Outcome], cell_updates: Callable[[int], float]
     work = sum(cell_updates(o.rid) for o in ok)
     return dict(shots=len(ok), failed=len(outcomes) - len(ok),
                 makespan_s=t_end - t_first, shots_per_s=len(ok) / (t_end - t_first),
-                p50_latency_s=q(0.50), p99_latency_s=q(0.99), mean_latency_s=sum(lat) / len(lat),
+                p50_latency_s=q(0.50), p90_latency_s=q(0.90), p99_latency_s=q(0.99),
+                max_latency_s=lat[-1], mean_latency_s=sum(lat) / len(lat),
                 gcell_per_s=work / (t_end - t_first) / 1e9)
 
 
@@ -262,10 +272,21 @@ class TorchDevice:
             entries = [(h["model"], h["state"], h["shot"], h["traces"]) for h in handles]
             for i in range(0, len(entries), self._abi.FD_BATCH_MAX):
                 step_batch(entries[i:i + self._abi.FD_BATCH_MAX], nsteps, stream=self.stream)
-            return [h for h in handles if h["state"].next >= h["shot"].nt]
-        for h in handles:   # plain path: the whole shot in one call
-            h["model"].run_shot(h["state"], h["shot"], h["traces"], stream=self.stream)
-        return list(handles)
+            done = [h for h in handles if h["state"].next >= h["shot"].nt]
+        else:
+            for h in handles:   # plain path: the whole shot in one call
+                h["model"].run_shot(h["state"], h["shot"], h["traces"], stream=self.stream)
+            done = list(handles)
+        # the finished shots' health, read when their chunk has retired
+        for h in done:
+            h["flags"] = h["state"].check_finite(stream=self.stream)
+        return done
+
+    def health(self, h) -> Optional[str]:
+        """None for a finite final wavefield, else the reason the shot failed
+        (called once the chunk that finished it has completed)."""
+        f = int(h["flags"].item()) if "flags" in h else 0
+        return None if f == 0 else "non-finite wavefield (NaN or infinity)"
 
     def fence(self):
         ev = torch.cuda.Event(enable_timing=True)

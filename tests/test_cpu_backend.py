@@ -214,3 +214,35 @@ def test_stream_probe(cpu):
     assert gbs > 0.1
     with pytest.raises(Exception):
         cpu.stream_probe(10, 1)
+
+
+def test_check_finite_reports_planted_values(cpu):
+    """fd_check_finite on the host back-end: a healthy shot reports 0; a NaN
+    or an infinity planted in P through fd_set_wavefield spreads through the
+    update and is still reported after further steps, in both levels."""
+    p = fi.layered3d(nx=40, ny=36, nz=30, nt=30)
+    m, s, shot, _ = run_cpu(cpu, p)
+    assert s.check_finite() == 0
+    for bad in (np.nan, np.inf, -np.inf):
+        s2 = m.new_state()
+        s2.begin(shot)
+        for n in range(5):
+            s2.step(shot, n)
+        f = s2.wavefield(0).copy()
+        f.reshape(-1)[f.size // 3] = bad
+        s2.set_wavefield(0, f)
+        assert s2.check_finite() == 5          # P, and a non-finite input
+        for n in range(5, 9):
+            s2.step(shot, n)
+        assert s2.check_finite() == 7          # spread into both levels
+        w = s2.wavefield(0)
+        assert np.count_nonzero(~np.isfinite(w)) > 1
+    s2.begin(shot)
+    assert s2.check_finite() == 0              # a new shot clears the flags
+    w = p.wavelet().copy()
+    w[7] = np.nan
+    s2.begin(cpu.Shot(p.src, w, receivers_of(p)))
+    assert s2.check_finite() == 4              # a non-finite wavelet sample
+    fresh = m.new_state()
+    with pytest.raises(cpu.FDError):
+        fresh.check_finite()                   # no shot begun
