@@ -357,6 +357,27 @@ fd_status fd_step_batch(fd_batch_item *items, int32_t count, int32_t nsteps, voi
 fd_status fd_step_routines(const fd_model *model, fd_state *state, const fd_shot *shot, int64_t n,
                            float *trace_row, void *work, size_t work_bytes, void *stream);
 
+/* FD_ROUTINES_STATIC_BYTES: the size of the library's static work area. */
+#define FD_ROUTINES_STATIC_BYTES ((size_t)64 << 20)
+
+/* fd_step_routines for callers that cannot allocate device memory (code
+ * under stream or graph capture, serving loops that forbid allocation,
+ * harnesses without an allocator): the derivative fields live in a work
+ * area of FD_ROUTINES_STATIC_BYTES (64 MiB) that the library holds in each
+ * GPU's memory from the time it is loaded until the process ends, instead of
+ * a `work` argument.  Nothing is allocated or freed: its address on the
+ * stream's device is looked up on the first call that uses that device and
+ * kept.  Grids whose routine work (fd_sizes.routines_work: ndim padded FP32
+ * fields) exceeds the area are rejected with FD_ERR_INVALID_ARG before any
+ * launch (e.g. 2D up to 2048 x 4096, 3D up to about 5.5 M padded cells).
+ * Every call on one GPU shares that GPU's area: calls that overlap on one
+ * GPU (different streams, or threads without ordering) race and give
+ * undefined results; calls ordered on one stream are safe.  The area starts
+ * undefined and nothing in it needs clearing (every step rewrites what it
+ * reads).  Otherwise identical to fd_step_routines, bit for bit. */
+fd_status fd_step_routines_noalloc(const fd_model *model, fd_state *state, const fd_shot *shot,
+                                   int64_t n, float *trace_row, void *stream);
+
 /* The practical memory roof the step kernels are measured against (the
  * role the measured stream bandwidth plays under the roofline of Section
  * 7): streams n floats through HBM with no stencil, kind 0 a copy (out = a;

@@ -300,6 +300,16 @@ class State:
                               _stream_handle(stream))
         self.next = n + 1
 
+    def step_routines_noalloc(self, shot: Shot, n: int, trace_row: Optional[torch.Tensor] = None,
+                              stream=None) -> None:
+        """Step n as one kernel per routine with the library's static work
+        area (fd_step_routines_noalloc): no buffer is allocated or passed;
+        grids whose routine work exceeds the area raise FDError."""
+        _abi.fd_step_routines_noalloc(self.model.handle, self.handle, shot._c, n,
+                                      trace_row.data_ptr() if trace_row is not None else None,
+                                      _stream_handle(stream))
+        self.next = n + 1
+
     def check_finite(self, flags: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
         """Enqueues fd_check_finite: returns a device int32 tensor of one
         element whose bit 0 (P) and bit 1 (Pold) are set when that level

@@ -87,6 +87,7 @@ SIGNATURES = [
     ("fd_set_wavefield", ctypes.c_int, [_P, _I32, _P, _P]),
     ("fd_step_batch", ctypes.c_int, [ctypes.POINTER(fd_batch_item), _I32, _I32, _P]),
     ("fd_step_routines", ctypes.c_int, [_P, _P, ctypes.POINTER(fd_shot), _I64, _P, _P, _SZ, _P]),
+    ("fd_step_routines_noalloc", ctypes.c_int, [_P, _P, ctypes.POINTER(fd_shot), _I64, _P, _P]),
     ("fd_slab_exchange", ctypes.c_int, [_P, _P, _P]),
     ("fd_check_finite", ctypes.c_int, [_P, _P, _P]),
     ("fd_stream_probe", ctypes.c_int, [_I32, _P, _P, _P, _SZ, _P]),
@@ -169,12 +170,21 @@ def fd_step_routines(model: int, state: int, shot: fd_shot, n: int, trace_row_pt
                                  work_bytes, stream))
 
 
+def fd_step_routines_noalloc(model: int, state: int, shot: fd_shot, n: int, trace_row_ptr,
+                             stream: int) -> None:
+    check(lib().fd_step_routines_noalloc(model, state, ctypes.byref(shot), n, trace_row_ptr, stream))
+
+
 def fd_stream_probe(kind: int, a_ptr: int, b_ptr, out_ptr: int, n: int, stream: int) -> None:
     check(lib().fd_stream_probe(kind, a_ptr, b_ptr, out_ptr, n, stream))
 
 
 def fd_check_finite(state: int, flags_ptr: int, stream: int) -> None:
     check(lib().fd_check_finite(state, flags_ptr, stream))
+
+
+# size of the library's static work area (FD_ROUTINES_STATIC_BYTES)
+ROUTINES_STATIC_BYTES = 64 << 20
 
 
 def fd_run_shot(model: int, state: int, shot: fd_shot, traces_ptr, ckpt_ptr, ckpt_bytes: int,

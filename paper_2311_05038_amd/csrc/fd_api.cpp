@@ -656,8 +656,12 @@ fd_status fd_slab_exchange(const fd_state *upper, const fd_state *lower, void *s
     return ok();
 }
 
-fd_status fd_step_routines(const fd_model *model, fd_state *state, const fd_shot *shot, int64_t n,
-                           float *trace_row, void *work, size_t work_bytes, void *stream)
+}  // extern "C"
+
+namespace {
+
+fd_status step_routines(const fd_model *model, fd_state *state, const fd_shot *shot, int64_t n,
+                        float *trace_row, void *work, size_t work_bytes, bool static_work, hipStream_t s)
 {
     if (!model || !state) return fail(FD_ERR_INVALID_ARG, "NULL model or state");
     if (state->m != model) return fail(FD_ERR_INVALID_ARG, "state was created for another model");
@@ -666,15 +670,26 @@ fd_status fd_step_routines(const fd_model *model, fd_state *state, const fd_shot
     const Layout &L = model->L;
     if (L.storage != FD_F32) return fail(FD_ERR_UNSUPPORTED, "the routine-per-kernel step is built for FP32 fields only");
     if (is_slab(L)) return fail(FD_ERR_UNSUPPORTED, "the routine-per-kernel step is not built for z-slabs");
-    if (!work) return fail(FD_ERR_INVALID_ARG, "work is NULL");
-    if (work_bytes < (size_t)L.ndim * L.f32field)
-        return fail(FD_ERR_INVALID_ARG, "work holds %zu bytes, %zu needed", work_bytes,
-                    (size_t)L.ndim * L.f32field);
+    const size_t need = (size_t)L.ndim * L.f32field;
+    if (static_work) {
+        if (need > fdk::kRoutinesScratchBytes)
+            return fail(FD_ERR_INVALID_ARG,
+                        "the grid's routine work (%zu bytes) exceeds the static work area (%zu bytes); "
+                        "fd_step_routines takes a work buffer of any size",
+                        need, fdk::kRoutinesScratchBytes);
+    } else {
+        if (!work) return fail(FD_ERR_INVALID_ARG, "work is NULL");
+        if (work_bytes < need) return fail(FD_ERR_INVALID_ARG, "work holds %zu bytes, %zu needed", work_bytes, need);
+    }
     if (state->next < 0) return fail(FD_ERR_INVALID_ARG, "fd_begin_shot has not been called");
     if (n != state->next) return fail(FD_ERR_INVALID_ARG, "step %lld requested, next step is %lld",
                                       (long long)n, (long long)state->next);
     if (n >= shot->nt) return fail(FD_ERR_INVALID_ARG, "step %lld beyond the shot's %lld steps",
                                    (long long)n, (long long)shot->nt);
+    if (static_work) {
+        const hipError_t e = fdk::routines_scratch(s, &work);
+        if (e != hipSuccess) return hip_fail(e, "static work area of the routine step");
+    }
     StepArgs a = base_args(model, shot);
     a.cur = state->buf[n & 1];
     a.prev = state->buf[(n + 1) & 1];
@@ -683,10 +698,27 @@ fd_status fd_step_routines(const fd_model *model, fd_state *state, const fd_shot
     char *w = (char *)work;
     float *dzz = (float *)w, *dxx = (float *)(w + L.f32field);
     float *dyy = L.ndim == 3 ? (float *)(w + 2 * L.f32field) : nullptr;
-    hipError_t e = fdk::launch_routines(a, L.ndim, dzz, dxx, dyy, (hipStream_t)stream);
+    hipError_t e = fdk::launch_routines(a, L.ndim, dzz, dxx, dyy, s);
     if (e != hipSuccess) return hip_fail(e, "routine kernels launch");
     state->next = n + 1;
     return ok();
+}
+
+}  // namespace
+
+extern "C" {
+
+fd_status fd_step_routines(const fd_model *model, fd_state *state, const fd_shot *shot, int64_t n,
+                           float *trace_row, void *work, size_t work_bytes, void *stream)
+{
+    return step_routines(model, state, shot, n, trace_row, work, work_bytes, false, (hipStream_t)stream);
+}
+
+fd_status fd_step_routines_noalloc(const fd_model *model, fd_state *state, const fd_shot *shot,
+                                   int64_t n, float *trace_row, void *stream)
+{
+    static_assert(fdk::kRoutinesScratchBytes == FD_ROUTINES_STATIC_BYTES, "static work area size");
+    return step_routines(model, state, shot, n, trace_row, nullptr, 0, true, (hipStream_t)stream);
 }
 
 fd_status fd_step_batch(fd_batch_item *items, int32_t count, int32_t nsteps, void *stream)

@@ -28,6 +28,11 @@ hipError_t launch_step_batch2d(Batch2D &b, int mode, hipStream_t s);
 // 3D, dyy materialised in HBM); FP32 fields only.
 hipError_t launch_routines(const StepArgs &a, int ndim, float *dzz, float *dxx, float *dyy,
                            hipStream_t s);
+// Size of the routine step's static work area (one per device, held from
+// load to process end), and its device address on the stream's device
+// (looked up once per device; nothing is allocated).
+constexpr size_t kRoutinesScratchBytes = (size_t)64 << 20;
+hipError_t routines_scratch(hipStream_t s, void **ptr);
 hipError_t launch_fill_u32(void *p, size_t nwords, uint32_t val, hipStream_t s);
 // Memory-roof probe: kind 0 out = a, kind 1 out = a + b * out (n floats,
 // a multiple of 4, 16-byte aligned arrays).

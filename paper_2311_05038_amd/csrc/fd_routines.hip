@@ -8,6 +8,8 @@
 // for operation, so both give the same bits.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "fd_device.hpp"
 #include "fd_launch.hpp"
 
@@ -187,7 +189,43 @@ __global__ void k_add_source(StepArgs a)
 
 int blocks_for(int64_t items, int threads) { return (int)((items + threads - 1) / threads); }
 
+constexpr int kMaxDevices = 64;
+
 }  // namespace
+
+// The work area of the routine-per-kernel step for callers that cannot
+// allocate: every GPU the library is loaded on holds its own copy.  In host
+// code this name stands for the symbol only; the device address comes from
+// routines_scratch().
+static __device__ __align__(256) unsigned char scratch[kRoutinesScratchBytes];
+
+hipError_t routines_scratch(hipStream_t s, void **ptr)
+{
+    static std::mutex mu;
+    static void *addr[kMaxDevices] = {};
+    int dev = 0;
+    hipError_t e = s != nullptr ? hipStreamGetDevice(s, &dev) : hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(mu);
+    if (addr[dev] == nullptr) {
+        // the symbol's address on `dev`, looked up with `dev` current
+        int cur = 0;
+        e = hipGetDevice(&cur);
+        if (e == hipSuccess && cur != dev) e = hipSetDevice(dev);
+        void *p = nullptr;
+        if (e == hipSuccess) e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (cur != dev) {
+            const hipError_t e2 = hipSetDevice(cur);
+            if (e == hipSuccess) e = e2;
+        }
+        if (e != hipSuccess) return e;
+        if (p == nullptr || (uintptr_t)p % 256 != 0) return hipErrorInvalidSymbol;
+        addr[dev] = p;
+    }
+    *ptr = addr[dev];
+    return hipSuccess;
+}
 
 hipError_t launch_routines(const StepArgs &a, int ndim, float *dzz, float *dxx, float *dyy,
                            hipStream_t s)

@@ -751,6 +751,11 @@ fd_status fd_step_routines(const fd_model *, fd_state *, const fd_shot *, int64_
     return unsupported("fd_step_routines");
 }
 
+fd_status fd_step_routines_noalloc(const fd_model *, fd_state *, const fd_shot *, int64_t, float *, void *)
+{
+    return unsupported("fd_step_routines_noalloc");
+}
+
 fd_status fd_stream_probe(int32_t, const float *, const float *, float *, size_t, void *)
 {
     return unsupported("fd_stream_probe (the host roof is fd_cpu_stream_probe)");
