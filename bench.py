@@ -616,26 +616,28 @@ def summarize_profiles(kt_dir: str, fetch_dir: str, write_dir: str, kernel: str 
     import hashlib
     stats = _csv_rows(kt_dir, "kernel_stats.csv")
     trace = _csv_rows(kt_dir, "kernel_trace.csv")
-    step = [r for r in trace if r.get("Kernel_Name", "").startswith(f"void fdk::{kernel}") or
-            kernel in r.get("Kernel_Name", "").split("<")[0]]
+    # kernel names as rocprofv3 -T gives them (the function's base name); the
+    # copy probe's dispatches are told from the step-pattern probe's by their
+    # grid (one thread per float4 of the 1 GiB arrays)
+    copy_threads = copy_bytes // 16
+    step = [r for r in trace if r["Kernel_Name"].startswith(kernel)]
     durs = sorted((int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) / 1e3 for r in step)
     avg = sum(durs) / len(durs)
 
-    def per_dispatch(rows, name_part, counter):
+    def per_dispatch(rows, name, counter, grid=None):
         vals = {}
         for r in rows:
-            if r.get("Counter_Name") == counter and name_part in r.get("Kernel_Name", ""):
-                vals.setdefault(r["Dispatch_Id"], 0.0)
-                vals[r["Dispatch_Id"]] += float(r["Counter_Value"])
+            if (r.get("Counter_Name") == counter and r["Kernel_Name"].startswith(name) and
+                    (grid is None or int(r["Grid_Size"]) == grid)):
+                vals[r["Dispatch_Id"]] = vals.get(r["Dispatch_Id"], 0.0) + float(r["Counter_Value"])
         return list(vals.values())
 
     fetch_rows = _csv_rows(fetch_dir, "counter_collection.csv")
     write_rows = _csv_rows(write_dir, "counter_collection.csv")
     f_step = per_dispatch(fetch_rows, kernel, "FETCH_SIZE")
     w_step = per_dispatch(write_rows, kernel, "WRITE_SIZE")
-    # the copy probe: kind 0 dispatches only (the kind 1 probe runs on 512^3)
-    f_copy = [v for v in per_dispatch(fetch_rows, copy_kernel + "<0>", "FETCH_SIZE")]
-    w_copy = [v for v in per_dispatch(write_rows, copy_kernel + "<0>", "WRITE_SIZE")]
+    f_copy = per_dispatch(fetch_rows, copy_kernel, "FETCH_SIZE", copy_threads)
+    w_copy = per_dispatch(write_rows, copy_kernel, "WRITE_SIZE", copy_threads)
     mean = lambda x: sum(x) / len(x)
     kib = copy_bytes / 1024
     fscale, wscale = kib / mean(f_copy), kib / mean(w_copy)
@@ -653,8 +655,7 @@ def summarize_profiles(kt_dir: str, fetch_dir: str, write_dir: str, kernel: str 
         json.dump(rec, fh, indent=1)
     lines = ["| kernel | calls | total ms | avg us | min us | max us | % |", "|---|---|---|---|---|---|---|"]
     for r in sorted(stats, key=lambda r: -float(r.get("TotalDurationNs", 0)))[:8]:
-        nm = r["Name"].split("(")[0].replace("void ", "").replace("fdk::", "")
-        nm = nm.split("<")[0] + ("<...>" if "<" in nm else "")
+        nm = r["Name"]
         lines.append(f"| {nm} | {r['Calls']} | {float(r['TotalDurationNs']) / 1e6:.2f} | "
                      f"{float(r['AverageNs']) / 1e3:.2f} | {float(r['MinNs']) / 1e3:.2f} | "
                      f"{float(r['MaxNs']) / 1e3:.2f} | {float(r['Percentage']):.2f} |")
