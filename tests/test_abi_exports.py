@@ -114,3 +114,32 @@ def test_z_slab_sizes_and_validation_on_host():
         assert e.value.status == status, kw
     _abi.fd_query_bytes(fd.Grid(**{**base, "slab_z0": 24}).c())   # the last 16 planes
     assert _abi.lib().fd_slab_exchange(None, None, None) == _abi.FD_ERR_INVALID_ARG
+
+
+def test_probe_health_and_noalloc_validate_before_launching():
+    """Argument errors of fd_stream_probe, fd_check_finite and
+    fd_step_routines_noalloc come back as statuses before any launch (the
+    pointers below are never dereferenced: every call fails validation)."""
+    from paper_2311_05038_amd import _abi
+    lib = _abi.lib()
+    A = 1 << 20                                 # a 16-byte aligned stand-in address
+    for args, what in [((2, A, A, A, 16, None), b"kind"),
+                       ((-1, A, A, A, 16, None), b"kind"),
+                       ((0, None, None, A, 16, None), b"NULL"),
+                       ((1, A, None, A, 16, None), b"NULL"),
+                       ((0, A, None, None, 16, None), b"NULL"),
+                       ((0, A, None, A, 18, None), b"multiple of 4"),
+                       ((0, A + 4, None, A, 16, None), b"aligned"),
+                       ((1, A, A + 8, A, 16, None), b"aligned"),
+                       ((1, A, A, A + 12, 16, None), b"aligned")]:
+        assert lib.fd_stream_probe(*args) == _abi.FD_ERR_INVALID_ARG, args
+        assert what in lib.fd_last_error(), (args, lib.fd_last_error())
+    assert lib.fd_check_finite(None, A, None) == _abi.FD_ERR_INVALID_ARG
+    shot = _abi.fd_shot()
+    assert lib.fd_step_routines_noalloc(None, None, ctypes.byref(shot), 0, None, None) \
+        == _abi.FD_ERR_INVALID_ARG
+    import os
+    import re
+    hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "fd.h")).read()
+    m = re.search(r"#define FD_ROUTINES_STATIC_BYTES \(\(size_t\)(\d+) << (\d+)\)", hdr)
+    assert m and _abi.ROUTINES_STATIC_BYTES == int(m.group(1)) << int(m.group(2))
