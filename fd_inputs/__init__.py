@@ -118,6 +118,8 @@ class Problem:
             return grf_velocity(self.shape, self.velocity_seed, corr_cells=200.0 / self.dh)
         if self.velocity_kind == "gradient":
             return gradient_velocity(self.shape)
+        if self.velocity_kind == "random":
+            return random_velocity(self.shape, self.velocity_seed, 1500.0, 3000.0)
         raise ValueError(self.velocity_kind)
 
     def rec_index(self) -> np.ndarray:
@@ -260,6 +262,39 @@ def random_velocity(shape: Tuple[int, ...], seed: int, vmin: float = 1500.0,
 # --------------------------------------------------------------------------
 # Workloads
 # --------------------------------------------------------------------------
+
+def random_geometry(seed: int) -> Problem:
+    """A small seeded workload of arbitrary shape, for sweeps that look for
+    shape-dependent mistakes (tile and chunk edges, axes shorter than the
+    stencil, odd strides): 2D or 3D, each axis drawn from sizes between 1 and
+    a few tiles (x up to 300), 1 to 13 steps, the source anywhere, a strided
+    receiver box anywhere (sometimes empty), sponge width 0-5 on a random set
+    of faces.  Velocities come from random_velocity(shape, seed, 1500, 3000)
+    (Courant number at most 0.3 with dh = 10 m, dt = 1 ms)."""
+    rng = np.random.default_rng(10_000 + seed)
+    ndim = 2 if rng.random() < 0.4 else 3
+    short = [1, 2, 3, 4, 5, 7, 8, 9, 12, 17, 31, 33, 40]
+    nz = int(rng.choice(short))
+    ny = 1 if ndim == 2 else int(rng.choice(short))
+    nx = int(rng.choice(short + [63, 65, 130, 257, 300]))
+    nt = int(rng.choice([1, 2, 5, 13]))
+    src = (int(rng.integers(nz)), 0 if ndim == 2 else int(rng.integers(ny)), int(rng.integers(nx)))
+
+    def axis(n):
+        d = int(rng.integers(1, 4))
+        o = int(rng.integers(n))
+        return o, int(rng.integers(1, (n - 1 - o) // d + 2)), d
+
+    (z0, cz, dz), (x0, cx, dx) = axis(nz), axis(nx)
+    y0, cy, dy = (0, 1, 1) if ndim == 2 else axis(ny)
+    rec = Receivers(z0, y0, x0, cz, cy, cx, dz, dy, dx)
+    if rng.random() < 0.1:
+        rec = Receivers(0, 0, 0, 0, 0, 0)
+    return Problem(name=f"random{seed}", ndim=ndim, nz=nz, ny=ny, nx=nx, dh=10.0, dt=1e-3, nt=nt,
+                   src=src, receivers=rec, f0=float(rng.choice([10.0, 20.0, 30.0])),
+                   sponge_width=int(rng.integers(0, 6)), sponge_faces=int(rng.integers(0, 64)),
+                   velocity_kind="random", velocity_seed=seed)
+
 
 def green2d() -> Problem:
     """2D homogeneous medium: 256x256, dh=10 m, v=2000 m/s, dt=0.5 ms, 500

@@ -386,7 +386,8 @@ fd_status fd_step_routines_noalloc(const fd_model *model, fd_state *state, const
  * per element), each in the configuration of its access pattern that
  * streams fastest on gfx950 (non-temporal stores; non-temporal loads for
  * kind 1, as in the step kernels).  a, b, out: device, 16-byte
- * aligned (b unused by kind 0), n a multiple of 4.  Stream-ordered; the
+ * aligned (b unused by kind 0), n a multiple of 4; n = 0 launches nothing
+ * and the arrays are not examined (they may be NULL).  Stream-ordered; the
  * caller times it with events on `stream`.  Errors: FD_ERR_INVALID_ARG for
  * an unknown kind, NULL or misaligned arrays or n not a multiple of 4. */
 fd_status fd_stream_probe(int32_t kind, const float *a, const float *b, float *out, size_t n, void *stream);

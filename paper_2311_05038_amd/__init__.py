@@ -163,7 +163,7 @@ class Model:
                  ckpt: Optional[torch.Tensor] = None, ckpt_every: int = 0,
                  stream=None) -> torch.Tensor:
         if traces is None:
-            traces = torch.empty((shot.nt, max(shot.nrec, 1)), dtype=torch.float32,
+            traces = torch.empty((shot.nt, shot.nrec), dtype=torch.float32,
                                  device=self.device)
         _abi.fd_run_shot(self.handle, state.handle, shot._c,
                          traces.data_ptr() if shot.nrec > 0 else None,
@@ -217,7 +217,7 @@ class Model:
         """fd_run_shots: every shot of `shots` with its own state (and
         checkpoint buffer); traces [nshots, nt, nrec]."""
         nt = shots[0].nt
-        nrec = max(shots[0].nrec, 1)
+        nrec = shots[0].nrec
         if traces is None:
             traces = torch.empty((len(shots), nt, nrec), dtype=torch.float32, device=self.device)
         _abi.fd_run_shots(self.handle, [st.handle for st in states], [s._c for s in shots],

@@ -129,7 +129,7 @@ class Model:
 
     def run_shot(self, state: "State", shot: Shot, traces: Optional[np.ndarray] = None) -> np.ndarray:
         if traces is None:
-            traces = np.empty((shot.nt, max(shot.nrec, 1)), dtype=np.float32)
+            traces = np.empty((shot.nt, shot.nrec), dtype=np.float32)
         check(lib().fd_run_shot(self.handle, state.handle, ctypes.byref(shot._c),
                                 _ptr(traces) if shot.nrec > 0 else None, None, 0, 0, None))
         state.next = shot.nt

@@ -619,6 +619,7 @@ fd_status fd_check_finite(const fd_state *state, uint32_t *flags, void *stream)
 fd_status fd_stream_probe(int32_t kind, const float *a, const float *b, float *out, size_t n, void *stream)
 {
     if (kind != 0 && kind != 1) return fail(FD_ERR_INVALID_ARG, "kind must be 0 (copy) or 1 (out = a + b * out)");
+    if (n == 0) return ok();  // nothing to stream; the arrays are not examined
     if (!a || !out || (kind == 1 && !b)) return fail(FD_ERR_INVALID_ARG, "NULL array");
     if (n % 4) return fail(FD_ERR_INVALID_ARG, "n must be a multiple of 4");
     if ((uintptr_t)a % 16 || (uintptr_t)out % 16 || (kind == 1 && (uintptr_t)b % 16))

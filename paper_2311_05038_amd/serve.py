@@ -259,7 +259,7 @@ class TorchDevice:
         model.buf.record_stream(self.stream)
         shot.wavelet.record_stream(self.stream)
         state = model.new_state()
-        traces = torch.empty((shot.nt, max(shot.nrec, 1)), dtype=torch.float32,
+        traces = torch.empty((shot.nt, shot.nrec), dtype=torch.float32,
                              device=velocity.device)
         h = dict(model=model, state=state, shot=shot, traces=traces, req=req)
         if self.batched:

@@ -134,6 +134,9 @@ def test_probe_health_and_noalloc_validate_before_launching():
                        ((1, A, A, A + 12, 16, None), b"aligned")]:
         assert lib.fd_stream_probe(*args) == _abi.FD_ERR_INVALID_ARG, args
         assert what in lib.fd_last_error(), (args, lib.fd_last_error())
+    # an empty stream launches nothing and does not look at the arrays
+    assert lib.fd_stream_probe(1, None, None, None, 0, None) == _abi.FD_OK
+    assert lib.fd_stream_probe(2, None, None, None, 0, None) == _abi.FD_ERR_INVALID_ARG
     assert lib.fd_check_finite(None, A, None) == _abi.FD_ERR_INVALID_ARG
     shot = _abi.fd_shot()
     assert lib.fd_step_routines_noalloc(None, None, ctypes.byref(shot), 0, None, None) \

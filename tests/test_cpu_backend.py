@@ -246,3 +246,26 @@ def test_check_finite_reports_planted_values(cpu):
     fresh = m.new_state()
     with pytest.raises(cpu.FDError):
         fresh.check_finite()                   # no shot begun
+
+
+@pytest.mark.parametrize("seed", range(24))
+def test_random_shapes_against_oracle(cpu, orc, seed):
+    """Seeded small workloads of arbitrary shape (axes from 1 cell up, 1-13
+    steps, source, receiver box and sponge faces anywhere): both levels and
+    the traces at the FP32 parity bar, and fd_step equal to fd_run_shot."""
+    p = fi.random_geometry(seed)
+    v = p.velocity()
+    m, s, shot, tr = run_cpu(cpu, p, v)
+    ref = oracle_run(orc, p, v)
+    n = p.receivers.count
+    if n:
+        assert orc.rel_l2(tr[:, :n], ref["traces"]) <= TOL
+    assert orc.rel_l2(s.wavefield(0).reshape(-1), ref["cur"].reshape(-1)) <= TOL
+    assert orc.rel_l2(s.wavefield(1).reshape(-1), ref["prev"].reshape(-1)) <= TOL
+    s2 = m.new_state()
+    s2.begin(shot)
+    tr2 = np.zeros_like(tr)
+    for k in range(p.nt):
+        s2.step(shot, k, tr2[k] if n else None)
+    assert np.array_equal(tr2, tr)
+    assert np.array_equal(s2.wavefield(0), s.wavefield(0))

@@ -1,0 +1,90 @@
+"""A seeded sweep of small workloads of arbitrary shape through the C ABI:
+2D and 3D, axes from 1 cell to a few tiles (so shorter than the stencil,
+one cell past a tile, ragged everywhere), 1 to 13 steps, the source and a
+strided receiver box anywhere (sometimes empty), sponge bands of 0-5 cells
+on random faces.  On each: the FP32 shot against the FP64 oracle (relative
+L2 <= 1e-4 on traces and on both levels), the same bits from the host
+back-end, fd_step equal to fd_run_shot bit for bit, and the 16-bit storage
+forms within 1.5x the oracle's own 16-bit emulation error against FP64, and
+within the error bars of their whole-shot tests wherever the format can
+represent the compared values."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import fd_inputs as fi
+import oracle
+from helpers import grid_of, receivers_of, rel_l2, run, setup
+
+pytestmark = pytest.mark.gpu
+
+SEEDS = range(24)
+FP64_TOL = {1: 1e-2, 2: 8e-2}
+
+
+def _ref(p, v):
+    return oracle.forward(oracle.grid_of(p), v.reshape(p.nz, p.ny, p.nx), p.wavelet(), p.nt, p.src,
+                          p.rec_index())
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_fp32_random_shape_against_oracle_and_host(seed):
+    p = fi.random_geometry(seed)
+    print(f"case {p.name} shape={p.shape} nt={p.nt} src={p.src} rec={p.receivers} "
+          f"sponge={p.sponge_width}/{p.sponge_faces:#x}", flush=True)
+    v = p.velocity()
+    model, state, shot = setup(p, v)
+    tr = model.run_shot(state, shot).clone()
+    cur, prev = state.wavefield(0).clone(), state.wavefield(1).clone()
+    # the same shot one fd_step at a time
+    state.begin(shot)
+    tr_step = torch.zeros_like(tr)
+    for n in range(p.nt):
+        state.step(shot, n, tr_step[n] if p.receivers.count else None)
+    torch.cuda.synchronize()
+    assert torch.equal(tr, tr_step)
+    assert torch.equal(cur, state.wavefield(0)) and torch.equal(prev, state.wavefield(1))
+    tr, cur, prev = tr.cpu().numpy(), cur.cpu().numpy(), prev.cpu().numpy()
+
+    ref = _ref(p, v)
+    if p.receivers.count:
+        assert rel_l2(tr[:, :p.receivers.count], ref["traces"]) <= 1e-4
+    assert rel_l2(cur, ref["cur"].reshape(cur.shape)) <= 1e-4
+    assert rel_l2(prev, ref["prev"].reshape(prev.shape)) <= 1e-4
+
+    from paper_2311_05038_amd import cpu
+    if not os.path.exists(cpu.LIB_PATH):
+        pytest.fail("libfd_cpu.so is not built")
+    m = cpu.Model(grid_of(p), v)
+    s = m.new_state()
+    tr_c = m.run_shot(s, cpu.Shot(p.src, p.wavelet(), receivers_of(p)))
+    assert np.array_equal(tr_c, tr)
+    assert np.array_equal(s.wavefield(0).reshape(cur.shape), cur)
+
+
+@pytest.mark.parametrize("storage", [1, 2])
+@pytest.mark.parametrize("seed", SEEDS)
+def test_16bit_random_shape_error_is_bounded(seed, storage):
+    p = fi.random_geometry(seed)
+    print(f"case {p.name} shape={p.shape} nt={p.nt} storage={storage}", flush=True)
+    v = p.velocity()
+    tr, cur = run(p, v, storage=storage)
+    ref = _ref(p, v)
+    emu = oracle.forward_half(oracle.grid_of(p), storage, v.reshape(p.nz, p.ny, p.nx), p.wavelet(), p.nt,
+                              p.src, p.rec_index())
+    n = p.receivers.count
+    e_gpu = rel_l2(cur, ref["cur"].reshape(cur.shape))
+    e_emu = rel_l2(emu["cur"], ref["cur"])
+    if n:
+        e_gpu = max(e_gpu, rel_l2(tr[:, :n], ref["traces"]))
+        e_emu = max(e_emu, rel_l2(emu["traces"], ref["traces"]))
+    print(f"error vs fp64: gpu {e_gpu:.3e}  emulation {e_emu:.3e}", flush=True)
+    assert e_gpu <= 1.5 * e_emu + 1e-4
+    # binary16 with one power-of-two scale per field spans about 2^-24 of
+    # the field's largest value: receivers still ahead of the wavefront can
+    # read values below that, which both sides store as zero.  The FP64 bar
+    # holds wherever the format can represent what is compared.
+    if e_emu <= FP64_TOL[storage]:
+        assert e_gpu <= FP64_TOL[storage]
