@@ -141,8 +141,9 @@ def stream_probe(cells: int = 512 ** 3, reps: int = 20):
 def small2d_leg(reps: int = 5):
     """Small 2D shots, where a step is too small to fill the GPU: the 256^2
     Green's-function case (500 steps) and a 1024^2 shot (2000 steps) as
-    single fd_run_shot calls (one launch per step), and 16 shots of the 256^2
-    case in one fd_run_shots call (one batched launch per step)."""
+    single fd_run_shot calls (one launch per step) and as recorded graphs
+    (fd_shot_graph_launch: one graph launch per shot), and 16 shots of the
+    256^2 case in one fd_run_shots call (one batched launch per step)."""
     import statistics
     import torch
     import fd_inputs as fi
@@ -166,10 +167,15 @@ def small2d_leg(reps: int = 5):
         return dict(us_per_step=round(us / steps, 2), mcell_per_s=round(cells * steps / us, 1),
                     spread_pct=round(100 * (max(ts) - min(ts)) / us, 1))
 
+    import paper_2311_05038_amd as fd
     for name, p in (("green2d_256", fi.green2d()), ("surface2d_1024", fi.surface2d(1024, 1024, 2000, seed=5))):
         model, state, shot = setup(p)
         tr = torch.empty((p.nt, p.receivers.count), device="cuda")
         out[name] = timed(lambda: model.run_shot(state, shot, tr), p.nt, p.ncells)
+        # the same shot recorded once as a graph (fd_shot_graph_*) and replayed
+        g = fd.ShotGraph(model, state, shot, tr)
+        out[name + "_graph"] = timed(g.launch, p.nt, p.ncells)
+        del g
     p = fi.green2d()
     model, _, shot = setup(p)
     states = [model.new_state() for _ in range(16)]

@@ -214,6 +214,38 @@ fd_status fd_run_shot(const fd_model *model, fd_state *state, const fd_shot *sho
                       float *traces, void *ckpt, size_t ckpt_bytes, int32_t ckpt_every,
                       void *stream);
 
+/* A recorded shot: the launches of fd_run_shot (without checkpoints) for
+ * one (model, state, shot, traces) captured once into a HIP graph, so that
+ * a shot on a grid too small to fill the GPU pays one graph launch instead
+ * of one kernel launch per step.  Section 7's roofline places the step at
+ * the memory bound; on small grids (e.g. 256^2) a step streams its bytes in
+ * less time than a kernel launch takes, and the launches, not the memory,
+ * set the pace.  Opaque handle. */
+typedef struct fd_shot_graph fd_shot_graph;
+
+/* Records fd_begin_shot and steps 0..nt-1 of `shot` on (model, state), with
+ * trace rows written to `traces` (device [nt][nrec], or NULL), into a graph
+ * and instantiates it.  Nothing runs on the device, and the state's step
+ * counter is left as it was.  The graph keeps addresses, not contents:
+ * every launch reads the model's buffer and the shot's wavelet as they are
+ * then, and rewrites the state and `traces`; the fd_shot struct itself
+ * (source cell, receivers, nt, wavelet address) is read only here.  The
+ * model and state handles, their buffers, the wavelet and `traces` must
+ * outlive the graph.  Errors (nothing recorded): FD_ERR_INVALID_ARG for NULL
+ * arguments, a state of another model or an invalid shot; FD_ERR_UNSUPPORTED
+ * on a z-slab; FD_ERR_DEVICE if the capture or instantiation fails;
+ * FD_ERR_OUT_OF_MEMORY for the host handle. */
+fd_status fd_shot_graph_create(const fd_model *model, fd_state *state, const fd_shot *shot, float *traces,
+                               fd_shot_graph **out);
+
+/* Enqueues the recorded shot on `stream`: the same work as fd_run_shot(model,
+ * state, shot, traces, NULL, 0, 0, stream), with the same bits.  Afterwards
+ * the state's next step is nt.  Launches that use one state must be ordered
+ * (they rewrite it).  Errors: FD_ERR_INVALID_ARG for NULL; FD_ERR_DEVICE if
+ * the launch fails. */
+fd_status fd_shot_graph_launch(fd_shot_graph *graph, void *stream);
+fd_status fd_shot_graph_destroy(fd_shot_graph *graph);
+
 /* Exact discrete adjoint of fd_run_shot: accumulates into grad_v (device,
  * dense FP64, +=) the gradient dJ/dv of a scalar J of the traces, given
  * adj = dJ/dtraces (device FP32 [nt][nrec]) and the checkpoints fd_run_shot

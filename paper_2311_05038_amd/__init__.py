@@ -24,7 +24,7 @@ from . import _abi
 from ._abi import (FDError, FD_BF16, FD_C_F32, FD_C_FIXED16, FD_F16, FD_F32, FD_BATCH_MAX,
                    fd_batch_item, fd_grid, fd_receivers, fd_shot, fd_sizes)
 
-__all__ = ["Grid", "Receivers", "Shot", "Model", "State", "FDError", "FD_F32", "FD_F16",
+__all__ = ["Grid", "Receivers", "Shot", "Model", "State", "ShotGraph", "FDError", "FD_F32", "FD_F16",
            "FD_BF16", "FD_C_F32", "FD_C_FIXED16", "step_batch", "slab_exchange", "ensure_built"]
 
 FACES_NO_TOP = 0x3E
@@ -345,6 +345,39 @@ class State:
         if h:
             try:
                 _abi.fd_destroy_state(h)
+            except Exception:
+                pass
+            self.handle = None
+
+
+class ShotGraph:
+    """fd_shot_graph_create: the launches of Model.run_shot(state, shot,
+    traces) recorded once into a HIP graph; launch() replays them (one graph
+    launch instead of one kernel launch per step).  The graph keeps the
+    addresses of the model, state, wavelet and traces, which this object
+    keeps alive; replays read their contents as they are then."""
+
+    def __init__(self, model: "Model", state: "State", shot: Shot,
+                 traces: Optional[torch.Tensor] = None):
+        if traces is None:
+            traces = torch.empty((shot.nt, shot.nrec), dtype=torch.float32, device=model.device)
+        if shot.nrec and (traces.dtype != torch.float32 or not traces.is_contiguous()
+                          or traces.numel() < shot.nt * shot.nrec):
+            raise ValueError("traces must be contiguous FP32 with nt x nrec entries")
+        self.model, self.state, self.shot, self.traces = model, state, shot, traces
+        self.handle = _abi.fd_shot_graph_create(model.handle, state.handle, shot._c,
+                                                traces.data_ptr() if shot.nrec > 0 else None)
+
+    def launch(self, stream=None) -> torch.Tensor:
+        _abi.fd_shot_graph_launch(self.handle, _stream_handle(stream))
+        self.state.next = self.shot.nt
+        return self.traces
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            try:
+                _abi.fd_shot_graph_destroy(h)
             except Exception:
                 pass
             self.handle = None

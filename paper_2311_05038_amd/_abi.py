@@ -91,6 +91,9 @@ SIGNATURES = [
     ("fd_slab_exchange", ctypes.c_int, [_P, _P, _P]),
     ("fd_check_finite", ctypes.c_int, [_P, _P, _P]),
     ("fd_stream_probe", ctypes.c_int, [_I32, _P, _P, _P, _SZ, _P]),
+    ("fd_shot_graph_create", ctypes.c_int, [_P, _P, _P, _P, ctypes.POINTER(_P)]),
+    ("fd_shot_graph_launch", ctypes.c_int, [_P, _P]),
+    ("fd_shot_graph_destroy", ctypes.c_int, [_P]),
     ("fd_last_error", ctypes.c_char_p, []),
     ("fd_version", ctypes.c_char_p, []),
 ]
@@ -177,6 +180,20 @@ def fd_step_routines_noalloc(model: int, state: int, shot: fd_shot, n: int, trac
 
 def fd_stream_probe(kind: int, a_ptr: int, b_ptr, out_ptr: int, n: int, stream: int) -> None:
     check(lib().fd_stream_probe(kind, a_ptr, b_ptr, out_ptr, n, stream))
+
+
+def fd_shot_graph_create(model: int, state: int, shot: fd_shot, traces_ptr) -> int:
+    out = _P()
+    check(lib().fd_shot_graph_create(model, state, ctypes.byref(shot), traces_ptr, ctypes.byref(out)))
+    return out.value
+
+
+def fd_shot_graph_launch(graph: int, stream: int) -> None:
+    check(lib().fd_shot_graph_launch(graph, stream))
+
+
+def fd_shot_graph_destroy(graph: int) -> None:
+    check(lib().fd_shot_graph_destroy(graph))
 
 
 def fd_check_finite(state: int, flags_ptr: int, stream: int) -> None:

@@ -259,6 +259,71 @@ fd_status fd_run_shot(const fd_model *model, fd_state *state, const fd_shot *sho
     return ok();
 }
 
+struct fd_shot_graph {
+    hipGraphExec_t exec;
+    fd_state *state;
+    int64_t nt;
+};
+
+fd_status fd_shot_graph_create(const fd_model *model, fd_state *state, const fd_shot *shot, float *traces,
+                               fd_shot_graph **out)
+{
+    if (!model || !state || !out) return fail(FD_ERR_INVALID_ARG, "NULL model, state or output handle");
+    *out = nullptr;
+    if (state->m != model) return fail(FD_ERR_INVALID_ARG, "state was created for another model");
+    fd_status st = check_shot(model, shot);
+    if (st != FD_OK) return st;
+    if (is_slab(model->L)) return fail(FD_ERR_UNSUPPORTED, "a z-slab steps with fd_step and fd_slab_exchange");
+    fd_shot_graph *h = new (std::nothrow) fd_shot_graph{};
+    if (!h) return fail(FD_ERR_OUT_OF_MEMORY, "cannot allocate the graph handle");
+    const int64_t next_before = state->next;  // recording advances the host counter only
+    // The launches are recorded on a private stream (default priority) and
+    // replayed on the caller's: the capture itself runs nothing.
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        if (cs) (void)hipStreamDestroy(cs);
+        delete h;
+        return hip_fail(e, "graph capture start");
+    }
+    st = do_begin(model, state, shot, cs);
+    const int64_t nrec = nrec_of(shot);
+    for (int64_t n = 0; st == FD_OK && n < shot->nt; ++n)
+        st = do_step(model, state, shot, n, traces ? traces + (size_t)n * (size_t)nrec : nullptr, cs);
+    hipGraph_t g = nullptr;
+    e = hipStreamEndCapture(cs, &g);  // ends the capture whether or not recording succeeded
+    if (st == FD_OK && e == hipSuccess) e = hipGraphInstantiate(&h->exec, g, nullptr, nullptr, 0);
+    if (g) (void)hipGraphDestroy(g);
+    (void)hipStreamDestroy(cs);
+    if (st == FD_OK && e != hipSuccess) st = hip_fail(e, "graph capture");
+    state->next = next_before;  // nothing ran on the device
+    if (st != FD_OK) {
+        delete h;
+        return st;
+    }
+    h->state = state;
+    h->nt = shot->nt;
+    *out = h;
+    return ok();
+}
+
+fd_status fd_shot_graph_launch(fd_shot_graph *g, void *stream)
+{
+    if (!g) return fail(FD_ERR_INVALID_ARG, "NULL graph");
+    const hipError_t e = hipGraphLaunch(g->exec, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "graph launch");
+    g->state->next = g->nt;
+    return ok();
+}
+
+fd_status fd_shot_graph_destroy(fd_shot_graph *g)
+{
+    if (g) (void)hipGraphExecDestroy(g->exec);
+    delete g;
+    return ok();
+}
+
 fd_status fd_run_shots(const fd_model *model, fd_state *const *states, const fd_shot *const *shots,
                        int32_t count, float *const *traces, void *const *ckpt, size_t ckpt_bytes,
                        int32_t ckpt_every, void *stream)

@@ -761,4 +761,20 @@ fd_status fd_stream_probe(int32_t, const float *, const float *, float *, size_t
     return unsupported("fd_stream_probe (the host roof is fd_cpu_stream_probe)");
 }
 
+fd_status fd_shot_graph_create(const fd_model *, fd_state *, const fd_shot *, float *, fd_shot_graph **out)
+{
+    if (out) *out = nullptr;
+    return unsupported("fd_shot_graph_create (a host shot has no launches to record)");
+}
+
+fd_status fd_shot_graph_launch(fd_shot_graph *, void *)
+{
+    return unsupported("fd_shot_graph_launch");
+}
+
+fd_status fd_shot_graph_destroy(fd_shot_graph *)
+{
+    return FD_OK;
+}
+
 }  // extern "C"

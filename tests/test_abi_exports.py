@@ -116,12 +116,14 @@ def test_z_slab_sizes_and_validation_on_host():
     assert _abi.lib().fd_slab_exchange(None, None, None) == _abi.FD_ERR_INVALID_ARG
 
 
-def test_probe_health_and_noalloc_validate_before_launching():
-    """Argument errors of fd_stream_probe, fd_check_finite and
-    fd_step_routines_noalloc come back as statuses before any launch (the
-    pointers below are never dereferenced: every call fails validation)."""
+def test_probe_health_noalloc_and_graph_validate_before_launching():
+    """Argument errors of fd_stream_probe, fd_check_finite,
+    fd_step_routines_noalloc and the recorded-shot calls come back as
+    statuses before any launch (the pointers below are never dereferenced:
+    every call fails validation)."""
     from paper_2311_05038_amd import _abi
     lib = _abi.lib()
+    shot = _abi.fd_shot()
     A = 1 << 20                                 # a 16-byte aligned stand-in address
     for args, what in [((2, A, A, A, 16, None), b"kind"),
                        ((-1, A, A, A, 16, None), b"kind"),
@@ -134,11 +136,15 @@ def test_probe_health_and_noalloc_validate_before_launching():
                        ((1, A, A, A + 12, 16, None), b"aligned")]:
         assert lib.fd_stream_probe(*args) == _abi.FD_ERR_INVALID_ARG, args
         assert what in lib.fd_last_error(), (args, lib.fd_last_error())
+    out = ctypes.c_void_p(123)
+    assert lib.fd_shot_graph_create(None, None, ctypes.byref(shot), None, ctypes.byref(out)) \
+        == _abi.FD_ERR_INVALID_ARG
+    assert lib.fd_shot_graph_launch(None, None) == _abi.FD_ERR_INVALID_ARG
+    assert lib.fd_shot_graph_destroy(None) == _abi.FD_OK
     # an empty stream launches nothing and does not look at the arrays
     assert lib.fd_stream_probe(1, None, None, None, 0, None) == _abi.FD_OK
     assert lib.fd_stream_probe(2, None, None, None, 0, None) == _abi.FD_ERR_INVALID_ARG
     assert lib.fd_check_finite(None, A, None) == _abi.FD_ERR_INVALID_ARG
-    shot = _abi.fd_shot()
     assert lib.fd_step_routines_noalloc(None, None, ctypes.byref(shot), 0, None, None) \
         == _abi.FD_ERR_INVALID_ARG
     import os
