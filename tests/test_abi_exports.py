@@ -152,3 +152,32 @@ def test_probe_health_noalloc_and_graph_validate_before_launching():
     hdr = open(os.path.join(os.path.dirname(__file__), "..", "include", "fd.h")).read()
     m = re.search(r"#define FD_ROUTINES_STATIC_BYTES \(\(size_t\)(\d+) << (\d+)\)", hdr)
     assert m and _abi.ROUTINES_STATIC_BYTES == int(m.group(1)) << int(m.group(2))
+
+
+def test_last_error_is_per_thread():
+    """fd_last_error is thread-local: threads that fail different calls at
+    the same time each read back their own message."""
+    import threading
+    import paper_2311_05038_amd as fd
+    from paper_2311_05038_amd import _abi
+    lib = _abi.lib()
+    barrier = threading.Barrier(8)
+    seen = {}
+
+    def worker(k):
+        g = fd.Grid(ndim=2, nz=10 + k, ny=1, nx=10, dh=1.0, dt=1e-4, storage=7 + k).c()
+        barrier.wait()
+        for _ in range(200):
+            st = lib.fd_query_bytes(ctypes.byref(g), 1, 1, ctypes.byref(_abi.fd_sizes()))
+            msg = lib.fd_last_error().decode()
+            if st != _abi.FD_ERR_INVALID_ARG or f"storage kind {7 + k}" not in msg:
+                seen[k] = (st, msg)
+                return
+        seen[k] = "ok"
+
+    ts = [threading.Thread(target=worker, args=(k,)) for k in range(8)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    assert all(v == "ok" for v in seen.values()) and len(seen) == 8, seen
