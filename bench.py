@@ -705,7 +705,7 @@ Summary written by `python bench.py --summarize-profiles gpurun_out/prof/kt gpur
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=5, help="timed shots; their median and spread are reported beside the mean")
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--probe-only", action="store_true",
