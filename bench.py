@@ -321,12 +321,13 @@ def serve_leg(n_requests: int = 1000, seed: int = 50, n_sub: int = 500, sub_frac
                 log(f"[bench] serve {tag}: {done}/{total} shots done")
         # "batched": the earliest-arrived resident shot and then the shots
         # with the least remaining work advance, enough of them to give each
-        # launch 12 M cells per step, the others wait resident
+        # launch 20 M cells per step (fields that fit the Infinity Cache),
+        # the others wait resident
         for name, batched, slots, policy in (("batched", True, 64, "srpt_oldest"),
                                              ("sequential", False, 1, "all")):
             torch.cuda.synchronize()
             sch = Scheduler(TorchDevice(make_inputs, batched=batched), max_slots=slots,
-                            hbm_budget=200 << 30, chunk=25, policy=policy, launch_cells=12 << 20,
+                            hbm_budget=200 << 30, chunk=25, policy=policy, launch_cells=20 << 20,
                             progress=progress)
             o = sch.run(reqs)
             out[name] = {k: (round(v, 4) if isinstance(v, float) else v)
