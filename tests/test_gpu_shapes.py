@@ -7,7 +7,8 @@ L2 <= 1e-4 on traces and on both levels), the same bits from the host
 back-end, fd_step equal to fd_run_shot bit for bit, and the 16-bit storage
 forms within 1.5x the oracle's own 16-bit emulation error against FP64, and
 within the error bars of their whole-shot tests wherever the format can
-represent the compared values."""
+represent the compared values; and the checkpointed adjoint gradient against
+the oracle's discrete adjoint."""
 import os
 
 import numpy as np
@@ -88,3 +89,33 @@ def test_16bit_random_shape_error_is_bounded(seed, storage):
     # holds wherever the format can represent what is compared.
     if e_emu <= FP64_TOL[storage]:
         assert e_gpu <= FP64_TOL[storage]
+
+
+def _grad_gpu(p, v, resid, every):
+    model, state, shot = setup(p, v)
+    ck = model.checkpoint_buffer(p.nt, every)
+    model.run_shot(state, shot, ckpt=ck, ckpt_every=every)
+    g = torch.zeros(p.ncells, dtype=torch.float64, device="cuda")
+    model.adjoint_gradient(shot, torch.from_numpy(resid.astype(np.float32)).cuda(), ck, every, g)
+    torch.cuda.synchronize()
+    return g.cpu().numpy().reshape(p.shape)
+
+
+@pytest.mark.parametrize("seed", [s for s in SEEDS if fi.random_geometry(s).receivers.count])
+def test_gradient_random_shape_against_oracle(seed):
+    """The checkpointed adjoint gradient on the same shapes: against the
+    oracle's exact discrete adjoint at the gradient bar (relative L2 <=
+    1e-3), and equal bit for bit to the single-segment gradient whatever the
+    checkpoint interval (1, 2, 3 steps or the whole shot)."""
+    p = fi.random_geometry(seed)
+    every = (1, 2, 3, p.nt)[seed % 4]
+    print(f"case {p.name} shape={p.shape} nt={p.nt} every={every}", flush=True)
+    v = p.velocity()
+    resid = np.random.default_rng(seed).standard_normal((p.nt, p.receivers.count))
+    g = _grad_gpu(p, v, resid, every)
+    gv, _ = oracle.adjoint(oracle.grid_of(p), v.reshape(p.nz, p.ny, p.nx), p.wavelet(), p.nt, p.src,
+                           p.rec_index(), resid.astype(np.float32).astype(np.float64))
+    err = rel_l2(g, gv.reshape(g.shape))
+    print(f"gradient relL2 {err:.3e}", flush=True)
+    assert err <= 1e-3
+    assert np.array_equal(g, _grad_gpu(p, v, resid, p.nt))
