@@ -321,7 +321,13 @@ fd_status fd_get_wavefield(const fd_state *state, int32_t which, float *out, voi
  * (Listing 3's WaveSimulator exposes set/get methods).  With 16-bit storage
  * the level's scale is 2^(floor(log2 max|in|) - 11) and the values are
  * rounded to nearest even.  On a state that has not begun a shot, the state
- * is first put at rest with next step 0.  No source addition is made. */
+ * is first put at rest with next step 0.  No source addition is made.
+ * Resuming a shot: a shot stopped after k steps (P and Pold read with
+ * fd_get_wavefield) continues on a fresh state given both levels here, with
+ * a shot whose wavelet starts at sample k (its step n is step k + n of the
+ * original, trace row n is row k + n); with FP32 storage the continuation
+ * equals the uninterrupted shot bit for bit (16-bit storage re-derives the
+ * levels' scales from their values). */
 fd_status fd_set_wavefield(fd_state *state, int32_t which, const float *in, void *stream);
 
 /* Health of a shot.  Writes *flags (device, one 4-byte-aligned uint32):
