@@ -277,6 +277,13 @@ fd_status fd_shot_graph_create(const fd_model *model, fd_state *state, const fd_
     fd_shot_graph *h = new (std::nothrow) fd_shot_graph{};
     if (!h) return fail(FD_ERR_OUT_OF_MEMORY, "cannot allocate the graph handle");
     const int64_t next_before = state->next;  // recording advances the host counter only
+    {
+        // the tile plan of a 3D step asks the runtime for the kernel's
+        // occupancy once per storage kind; ask before the capture starts
+        int64_t skip = 0;
+        StepArgs a = base_args(model, shot, &skip);
+        fdk::plan_tiles(a, model->L.ndim, model->L.storage, false);
+    }
     // The launches are recorded on a private stream (default priority) and
     // replayed on the caller's: the capture itself runs nothing.
     hipStream_t cs = nullptr;

@@ -89,3 +89,31 @@ def test_recording_a_slab_is_refused():
     with pytest.raises(fd.FDError) as e:
         fd.ShotGraph(m, m.new_state(), fd.Shot(p.src, wav, fd.Receivers(0, 0, 0, 1, 1, 4)))
     assert e.value.status == fd._abi.FD_ERR_UNSUPPORTED
+
+
+def test_recording_before_any_eager_step_in_a_fresh_process():
+    """A process whose first 3D step is a recording: the step's launch plan
+    (an occupancy query, cached per process) is settled before the capture."""
+    import os
+    import subprocess
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    code = f"""
+import sys
+sys.path.insert(0, {os.path.dirname(here)!r}); sys.path.insert(0, {here!r})
+import torch
+import fd_inputs as fi
+import paper_2311_05038_amd as fd
+from helpers import setup
+p = fi.layered3d(nx=72, ny=40, nz=44, nt=30)
+model, state, shot = setup(p)
+g = fd.ShotGraph(model, state, shot)
+out = g.launch().clone()
+ref = model.run_shot(model.new_state(), shot)
+torch.cuda.synchronize()
+assert torch.equal(out, ref)
+print("recorded-first ok", flush=True)
+"""
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+    print(r.stdout[-2000:], r.stderr[-2000:], flush=True)
+    assert r.returncode == 0 and "recorded-first ok" in r.stdout
