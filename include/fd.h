@@ -403,9 +403,10 @@ fd_status fd_step_routines(const fd_model *model, fd_state *state, const fd_shot
  * harnesses without an allocator): the derivative fields live in a work
  * area of FD_ROUTINES_STATIC_BYTES (64 MiB) that the library holds in each
  * GPU's memory from the time it is loaded until the process ends, instead of
- * a `work` argument.  Nothing is allocated or freed: its address on the
- * stream's device is looked up on the first call that uses that device and
- * kept.  Grids whose routine work (fd_sizes.routines_work: ndim padded FP32
+ * a `work` argument.  Nothing is allocated or freed: its address on a
+ * device is looked up once and kept, by fd_create_model on that device (so
+ * before a capture that uses the model) or else by the first call that
+ * needs it.  Grids whose routine work (fd_sizes.routines_work: ndim padded FP32
  * fields) exceeds the area are rejected with FD_ERR_INVALID_ARG before any
  * launch (e.g. 2D up to 2048 x 4096, 3D up to about 5.5 M padded cells).
  * Every call on one GPU shares that GPU's area: calls that overlap on one

@@ -163,6 +163,17 @@ fd_status fd_create_model(const fd_grid *grid, const float *velocity, void *mode
             return hip_fail(e, "fd_create_model");
         }
     }
+    // Settle, outside any stream capture, what later launches on this device
+    // look up once and cache: the device address of the static routine work
+    // area of fd_step_routines_noalloc, and the 3D launch plan's occupancy.
+    // A failure here is left to the calls that need them, which report it.
+    {
+        void *area = nullptr;
+        (void)fdk::routines_scratch(s, &area);
+        StepArgs a = base_args(m, nullptr, nullptr);
+        fdk::plan_tiles(a, L.ndim, L.storage, false);
+        (void)hipGetLastError();
+    }
     *out = m;
     return ok();
 }

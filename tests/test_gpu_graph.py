@@ -117,3 +117,51 @@ print("recorded-first ok", flush=True)
     r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
     print(r.stdout[-2000:], r.stderr[-2000:], flush=True)
     assert r.returncode == 0 and "recorded-first ok" in r.stdout
+
+
+def test_noalloc_routine_step_first_used_under_capture():
+    """A process that first calls fd_step_routines_noalloc inside a stream
+    capture (torch.cuda.graph): the static area's address was settled when
+    the model was created, so the capture holds plain kernel launches, and
+    every replay gives the bits of the same steps run eagerly."""
+    import os
+    import subprocess
+    import sys
+    here = os.path.dirname(os.path.abspath(__file__))
+    code = f"""
+import sys
+sys.path.insert(0, {os.path.dirname(here)!r}); sys.path.insert(0, {here!r})
+import torch
+import fd_inputs as fi
+from helpers import setup
+p = fi.surface2d(64, 130, 12, seed=53)
+model, state, shot = setup(p)
+tr = torch.zeros((p.nt, p.receivers.count), device="cuda")
+g = torch.cuda.CUDAGraph()
+gs = torch.cuda.Stream()
+gs.wait_stream(torch.cuda.current_stream())
+with torch.cuda.stream(gs):
+    with torch.cuda.graph(g, stream=gs):
+        state.begin(shot, stream=gs)
+        for n in range(p.nt):
+            state.step_routines_noalloc(shot, n, tr[n], stream=gs)
+torch.cuda.synchronize()
+ref_state = model.new_state()
+ref_tr = torch.zeros_like(tr)
+ref_state.begin(shot)
+for n in range(p.nt):
+    ref_state.step_routines_noalloc(shot, n, ref_tr[n])
+ref_f = ref_state.wavefield(0)
+torch.cuda.synchronize()
+for r in range(3):
+    tr.zero_()
+    torch.cuda.synchronize()
+    g.replay()
+    torch.cuda.synchronize()
+    assert torch.equal(tr, ref_tr), r
+    assert torch.equal(state.wavefield(0), ref_f), r
+print("noalloc under capture ok", flush=True)
+"""
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, timeout=240)
+    print(r.stdout[-2000:], r.stderr[-2000:], flush=True)
+    assert r.returncode == 0 and "noalloc under capture ok" in r.stdout
