@@ -272,6 +272,79 @@ def adjoint_leg(nt: int = 2000, every: int = 50):
     return out
 
 
+# A tiny fd_stream_probe launch (SERVE_MARK_N floats: a grid of
+# SERVE_MARK_N / 4 threads that no other launch of the bench has) before and
+# after the batched 50/s serving run, so that a kernel trace can be cut to
+# that run (summarize_serving_trace).
+SERVE_MARK_N = 4 * 768
+
+
+def _serve_marker():
+    import torch
+    from paper_2311_05038_amd import _abi
+    a = torch.zeros(SERVE_MARK_N, device="cuda")
+    b = torch.zeros_like(a)
+    _abi.fd_stream_probe(0, a.data_ptr(), None, b.data_ptr(), SERVE_MARK_N,
+                         torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+
+
+def summarize_serving_trace(kt_dir: str, requests: int):
+    """GPU busy time of the batched serving run from a rocprofv3 kernel trace
+    (`--kernel-trace -f csv`) of `bench.py --legs serve`: the union of kernel
+    intervals between the two markers, the largest kernels and the gaps.
+    Writes profiles/k_step2d_batch_serving.md."""
+    import collections
+    import csv
+    import glob
+    path = sorted(glob.glob(os.path.join(kt_dir, "**", "*kernel_trace.csv"), recursive=True))[0]
+    rows = list(csv.DictReader(open(path)))
+    ks = sorted((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), r["Kernel_Name"],
+                 int(r.get("Grid_Size_X") or r.get("Grid_Size") or 0)) for r in rows)
+    marks = [k for k in ks if "k_stream" in k[2] and k[3] == SERVE_MARK_N // 4]
+    if len(marks) < 2:
+        raise SystemExit("the trace holds no pair of serving markers")
+    t0, t1 = marks[0][1], marks[1][0]
+    win = [k for k in ks if k[0] >= t0 and k[1] <= t1 and k is not marks[1]]
+    busy, cs, ce, gaps = 0, None, None, []
+    for s_, e_, _, _ in win:
+        if ce is None or s_ > ce:
+            if ce is not None:
+                busy += ce - cs
+                gaps.append(s_ - ce)
+            cs, ce = s_, e_
+        else:
+            ce = max(ce, e_)
+    busy += ce - cs
+    span = t1 - t0
+    tot = collections.Counter()
+    cnt = collections.Counter()
+    for s_, e_, n, _ in win:
+        tot[n.split("(")[0]] += e_ - s_
+        cnt[n.split("(")[0]] += 1
+    gaps.sort()
+    cmd = f"python -u bench.py --steps 1 --warmup 0 --no-cpu --legs serve --serve-requests {requests}"
+    lines = [f"# Batched serving ({requests} Poisson 2D shots at 50/s): GPU busy time", "",
+             "Kernel trace:", "",
+             "    cd /tmp && export TMPDIR=/tmp",
+             f"    rocprofv3 --kernel-trace -T -f csv -d gpurun_out/prof/serve -o sv -- {cmd}", "",
+             "The window runs from the end of the first serving marker (a "
+             f"{SERVE_MARK_N // 4}-thread fd_stream_probe launch) to the start of the second, "
+             "around the batched run of the 50/s stream.", "",
+             f"Window {span / 1e9:.3f} s; kernels running {busy / 1e9:.3f} s "
+             f"(**{100 * busy / span:.1f}%**); {len(win)} launches; "
+             f"{len(gaps)} gaps totalling {sum(gaps) / 1e9:.3f} s "
+             f"(median {gaps[len(gaps) // 2] / 1e3:.1f} us, largest {gaps[-1] / 1e6:.2f} ms).", "",
+             "| kernel | launches | total s | avg us |", "|---|---|---|---|"]
+    for n, t in tot.most_common(8):
+        lines.append(f"| {n} | {cnt[n]} | {t / 1e9:.3f} | {t / cnt[n] / 1e3:.1f} |")
+    lines += ["", f"Summary written by `python bench.py --summarize-serving-trace gpurun_out/prof/serve "
+                  f"--serve-requests {requests}`.", ""]
+    with open(os.path.join(ROOT, "profiles", "k_step2d_batch_serving.md"), "w") as fh:
+        fh.write("\n".join(lines))
+    print(json.dumps(dict(window_s=span / 1e9, busy_frac=busy / span, launches=len(win))))
+
+
 def serve_leg(n_requests: int = 1000, seed: int = 50, n_sub: int = 500, sub_frac: float = 0.7):
     """Poisson streams of 2D shots on grids drawn from 512^2..2048x4096 (nt
     1000..4000), each shot with its own seeded random-field velocity model
@@ -329,7 +402,13 @@ def serve_leg(n_requests: int = 1000, seed: int = 50, n_sub: int = 500, sub_frac
             sch = Scheduler(TorchDevice(make_inputs, batched=batched), max_slots=slots,
                             hbm_budget=200 << 30, chunk=25, policy=policy, launch_cells=20 << 20,
                             progress=progress)
+            mark = tag == "50/s" and batched       # brackets for a kernel trace of this run
+            if mark:
+                _serve_marker()
             o = sch.run(reqs)
+            if mark:
+                torch.cuda.synchronize()
+                _serve_marker()
             out[name] = {k: (round(v, 4) if isinstance(v, float) else v)
                          for k, v in summarize(o, cells.get).items()}
             out[name]["peak_slots"] = sch.peak_slots
@@ -344,6 +423,7 @@ def serve_leg(n_requests: int = 1000, seed: int = 50, n_sub: int = 500, sub_frac
     res = {"rate50": run_pair(reqs, "50/s")}
     # sub-saturation: the first n_sub shots, seeded exponential gaps at
     # sub_frac of the rate the batched run sustained (by work, not count)
+    n_sub = min(n_sub, n_requests)
     sustained = res["rate50"]["batched"]["gcell_per_s"] * 1e9
     mean_work = float(np.mean([cells[r.rid] for r in reqs_in[:n_sub]]))
     rate = sub_frac * sustained / mean_work
@@ -717,11 +797,17 @@ def main():
     ap.add_argument("--serve-requests", type=int, default=1000)
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 CSV output (host only)")
+    ap.add_argument("--summarize-serving-trace", metavar="KT_DIR",
+                    help="GPU busy time of the batched serving run from a rocprofv3 kernel trace "
+                         "of --legs serve (writes profiles/k_step2d_batch_serving.md)")
     ap.add_argument("--oracle-table", action="store_true",
                     help="only the FP64 oracle's rate on samples of every configuration (host only)")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(*args.summarize_profiles)
+        return
+    if args.summarize_serving_trace:
+        summarize_serving_trace(args.summarize_serving_trace, args.serve_requests)
         return
     if args.oracle_table:
         print(json.dumps({"oracle_table": oracle_table()}), flush=True)
