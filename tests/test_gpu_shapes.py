@@ -7,8 +7,8 @@ L2 <= 1e-4 on traces and on both levels), the same bits from the host
 back-end, fd_step equal to fd_run_shot bit for bit, and the 16-bit storage
 forms within 1.5x the oracle's own 16-bit emulation error against FP64, and
 within the error bars of their whole-shot tests wherever the format can
-represent the compared values; and the checkpointed adjoint gradient against
-the oracle's discrete adjoint."""
+represent the compared values; and the checkpointed adjoint gradient and the
+reverse-time-migration image against the oracle's."""
 import os
 
 import numpy as np
@@ -119,3 +119,32 @@ def test_gradient_random_shape_against_oracle(seed):
     print(f"gradient relL2 {err:.3e}", flush=True)
     assert err <= 1e-3
     assert np.array_equal(g, _grad_gpu(p, v, resid, p.nt))
+
+
+def _image_gpu(p, v, data, every):
+    model, state, shot = setup(p, v)
+    ck = model.checkpoint_buffer(p.nt, every)
+    model.run_shot(state, shot, ckpt=ck, ckpt_every=every)
+    img = torch.zeros(p.ncells, dtype=torch.float64, device="cuda")
+    model.rtm_image(shot, torch.from_numpy(data.astype(np.float32)).cuda(), ck, every, img)
+    torch.cuda.synchronize()
+    return img.cpu().numpy().reshape(p.shape)
+
+
+@pytest.mark.parametrize("seed", [s for s in SEEDS if fi.random_geometry(s).receivers.count])
+def test_image_random_shape_against_oracle(seed):
+    """The reverse-time-migration image on the same shapes, with seeded
+    random data: against the oracle's FP64 zero-lag correlation (relative
+    L2 <= 1e-3), and equal bit for bit across checkpoint intervals."""
+    p = fi.random_geometry(seed)
+    every = (2, 3, p.nt, 1)[seed % 4]
+    print(f"case {p.name} shape={p.shape} nt={p.nt} every={every}", flush=True)
+    v = p.velocity()
+    data = np.random.default_rng(100 + seed).standard_normal((p.nt, p.receivers.count))
+    img = _image_gpu(p, v, data, every)
+    ref = oracle.image(oracle.grid_of(p), v.reshape(p.nz, p.ny, p.nx), p.wavelet(), p.nt, p.src,
+                       p.rec_index(), data.astype(np.float32).astype(np.float64))
+    err = rel_l2(img, ref.reshape(img.shape))
+    print(f"image relL2 {err:.3e}", flush=True)
+    assert err <= 1e-3
+    assert np.array_equal(img, _image_gpu(p, v, data, p.nt))
