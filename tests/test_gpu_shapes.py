@@ -7,8 +7,9 @@ L2 <= 1e-4 on traces and on both levels), the same bits from the host
 back-end, fd_step equal to fd_run_shot bit for bit, and the 16-bit storage
 forms within 1.5x the oracle's own 16-bit emulation error against FP64, and
 within the error bars of their whole-shot tests wherever the format can
-represent the compared values; and the checkpointed adjoint gradient and the
-reverse-time-migration image against the oracle's."""
+represent the compared values; the checkpointed adjoint gradient and the
+reverse-time-migration image against the oracle's; and z-slab splits of the
+3D shapes against the whole grid."""
 import os
 
 import numpy as np
@@ -148,3 +149,54 @@ def test_image_random_shape_against_oracle(seed):
     print(f"image relL2 {err:.3e}", flush=True)
     assert err <= 1e-3
     assert np.array_equal(img, _image_gpu(p, v, data, p.nt))
+
+
+def _slab_seeds():
+    out = []
+    for s in range(64):
+        p = fi.random_geometry(s)
+        if p.ndim == 3 and p.nz >= 8:
+            out.append(s)
+    return out[:8]
+
+
+@pytest.mark.parametrize("seed", _slab_seeds())
+def test_slabs_random_shape_equal_whole_grid(seed):
+    """The same shapes cut along z into 2 or 3 slabs of seeded uneven
+    heights (at least 4 planes each), stepped with the ghost exchange after
+    every step: traces and both levels equal the whole grid's bit for bit."""
+    import paper_2311_05038_amd as fd
+    p = fi.random_geometry(seed)
+    rng = np.random.default_rng(200 + seed)
+    k = min(int(rng.integers(2, 4)), p.nz // 4)
+    counts = [4 + int(x) for x in rng.multinomial(p.nz - 4 * k, [1.0 / k] * k)]
+    assert min(counts) >= 4 and sum(counts) == p.nz
+    print(f"case {p.name} shape={p.shape} nt={p.nt} slabs={counts}", flush=True)
+    v = p.velocity()
+    model, state, shot = setup(p, v)
+    ref_tr = model.run_shot(state, shot).cpu().numpy()
+    ref_cur, ref_old = state.wavefield(0).cpu().numpy(), state.wavefield(1).cpu().numpy()
+
+    vz = np.ascontiguousarray(v, dtype=np.float32).reshape(p.nz, p.ny, p.nx)
+    models, states, z0 = [], [], 0
+    for g in grid_of(p).slabs(counts):
+        models.append(fd.Model(g, torch.from_numpy(np.ascontiguousarray(vz[z0:z0 + g.nz]).reshape(-1)).cuda()))
+        states.append(models[-1].new_state())
+        z0 += g.nz
+
+    def exchange():
+        for up, low in zip(states[:-1], states[1:]):
+            fd.slab_exchange(up, low)
+
+    for st in states:
+        st.begin(shot)
+    exchange()
+    tr = torch.full((p.nt, p.receivers.count), float("nan"), device="cuda")
+    for n in range(p.nt):
+        for st in states:
+            st.step(shot, n, tr[n] if p.receivers.count else None)
+        exchange()
+    cur = torch.cat([st.wavefield(0) for st in states], 0).cpu().numpy()
+    old = torch.cat([st.wavefield(1) for st in states], 0).cpu().numpy()
+    assert np.array_equal(tr.cpu().numpy(), ref_tr)
+    assert np.array_equal(cur, ref_cur) and np.array_equal(old, ref_old)
