@@ -8,8 +8,9 @@ back-end, fd_step equal to fd_run_shot bit for bit, and the 16-bit storage
 forms within 1.5x the oracle's own 16-bit emulation error against FP64, and
 within the error bars of their whole-shot tests wherever the format can
 represent the compared values; the checkpointed adjoint gradient and the
-reverse-time-migration image against the oracle's; and z-slab splits of the
-3D shapes against the whole grid."""
+reverse-time-migration image against the oracle's; z-slab splits of the 3D
+shapes against the whole grid; and the 2D shapes batched together against
+each shot alone."""
 import os
 
 import numpy as np
@@ -200,3 +201,37 @@ def test_slabs_random_shape_equal_whole_grid(seed):
     old = torch.cat([st.wavefield(1) for st in states], 0).cpu().numpy()
     assert np.array_equal(tr.cpu().numpy(), ref_tr)
     assert np.array_equal(cur, ref_cur) and np.array_equal(old, ref_old)
+
+
+def test_batched_random_2d_shapes_equal_alone():
+    """The 2D shapes of the sweep (up to 16 grids of different sizes, shot
+    lengths and receiver boxes) stepped together with fd_step_batch, joining
+    at seeded staggered steps and advanced in seeded chunk lengths: every
+    shot's traces and final field equal the shot run alone, bit for bit."""
+    import paper_2311_05038_amd as fd
+    seeds = [s for s in range(64) if fi.random_geometry(s).ndim == 2][:16]
+    probs = [fi.random_geometry(s) for s in seeds]
+    print(f"case batch of {len(probs)}: " + " ".join(f"{p.shape}/{p.nt}" for p in probs), flush=True)
+    alone = []
+    for p in probs:
+        m, s, sh = setup(p, p.velocity())
+        alone.append((m.run_shot(s, sh).clone(), s.wavefield(0).clone()))
+    objs = [setup(p, p.velocity()) for p in probs]
+    traces = [torch.zeros((p.nt, p.receivers.count), device="cuda") for p in probs]
+    rng = np.random.default_rng(77)
+    joins = sorted(rng.integers(0, 10, len(probs)).tolist())
+    entries, waiting, t = [], list(range(len(probs))), 0
+    while waiting or any(e[1].next < e[2].nt for e in entries):
+        while waiting and joins[waiting[0]] <= t:
+            i = waiting.pop(0)
+            m, s, sh = objs[i]
+            s.begin(sh)
+            entries.append((m, s, sh, traces[i] if probs[i].receivers.count else None))
+        k = int(rng.integers(1, 4))
+        fd.step_batch(entries, k)
+        t += k
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        assert objs[i][1].next == p.nt, i
+        assert torch.equal(traces[i], alone[i][0]), (i, p.shape)
+        assert torch.equal(objs[i][1].wavefield(0), alone[i][1]), (i, p.shape)
