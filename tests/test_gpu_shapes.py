@@ -9,8 +9,8 @@ forms within 1.5x the oracle's own 16-bit emulation error against FP64, and
 within the error bars of their whole-shot tests wherever the format can
 represent the compared values; the checkpointed adjoint gradient and the
 reverse-time-migration image against the oracle's; z-slab splits of the 3D
-shapes against the whole grid; and the 2D shapes batched together against
-each shot alone."""
+shapes against the whole grid; the 2D shapes batched together against each
+shot alone; and the routine-per-kernel step against the fused one."""
 import os
 
 import numpy as np
@@ -235,3 +235,30 @@ def test_batched_random_2d_shapes_equal_alone():
         assert objs[i][1].next == p.nt, i
         assert torch.equal(traces[i], alone[i][0]), (i, p.shape)
         assert torch.equal(objs[i][1].wavefield(0), alone[i][1]), (i, p.shape)
+
+
+@pytest.mark.parametrize("seed", SEEDS)
+def test_routines_random_shape_equal_fused(seed):
+    """The step as one kernel per routine (fd_step_routines, with a work
+    buffer, and fd_step_routines_noalloc) on the same shapes: traces and
+    both levels equal the fused step's bit for bit."""
+    p = fi.random_geometry(seed)
+    print(f"case {p.name} shape={p.shape} nt={p.nt}", flush=True)
+    v = p.velocity()
+    model, state, shot = setup(p, v)
+    ref_tr = model.run_shot(state, shot).clone()
+    ref = (state.wavefield(0).clone(), state.wavefield(1).clone())
+    work = torch.empty(model.sizes.routines_work, dtype=torch.uint8, device="cuda")
+    for noalloc in (False, True):
+        st = model.new_state()
+        st.begin(shot)
+        tr = torch.zeros_like(ref_tr)
+        for n in range(p.nt):
+            row = tr[n] if p.receivers.count else None
+            if noalloc:
+                st.step_routines_noalloc(shot, n, row)
+            else:
+                st.step_routines(shot, n, work, row)
+        torch.cuda.synchronize()
+        assert torch.equal(tr, ref_tr), noalloc
+        assert torch.equal(st.wavefield(0), ref[0]) and torch.equal(st.wavefield(1), ref[1]), noalloc
