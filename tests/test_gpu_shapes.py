@@ -10,7 +10,8 @@ within the error bars of their whole-shot tests wherever the format can
 represent the compared values; the checkpointed adjoint gradient and the
 reverse-time-migration image against the oracle's; z-slab splits of the 3D
 shapes against the whole grid; the 2D shapes batched together against each
-shot alone; and the routine-per-kernel step against the fused one."""
+shot alone; the routine-per-kernel step against the fused one; and recorded
+shots against eager ones."""
 import os
 
 import numpy as np
@@ -262,3 +263,23 @@ def test_routines_random_shape_equal_fused(seed):
         torch.cuda.synchronize()
         assert torch.equal(tr, ref_tr), noalloc
         assert torch.equal(st.wavefield(0), ref[0]) and torch.equal(st.wavefield(1), ref[1]), noalloc
+
+
+@pytest.mark.parametrize("storage", [0, 2])
+@pytest.mark.parametrize("seed", SEEDS[::3])
+def test_recorded_random_shape_equals_eager(seed, storage):
+    """A recorded shot (fd_shot_graph_*) on the same shapes replays the bits
+    of the eager shot, twice in a row."""
+    import paper_2311_05038_amd as fd
+    p = fi.random_geometry(seed)
+    print(f"case {p.name} shape={p.shape} nt={p.nt} storage={storage}", flush=True)
+    model, state, shot = setup(p, p.velocity(), storage=storage)
+    ref_tr = model.run_shot(state, shot).clone()
+    ref_f = state.wavefield(0).clone()
+    st = model.new_state()
+    g = fd.ShotGraph(model, st, shot)
+    for r in range(2):
+        tr = g.launch()
+        torch.cuda.synchronize()
+        assert torch.equal(tr, ref_tr), r
+        assert torch.equal(st.wavefield(0), ref_f), r
