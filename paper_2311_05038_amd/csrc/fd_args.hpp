@@ -39,7 +39,8 @@ struct StepArgs {
     const float *gz, *gy, *gx;  // damping profiles (nz, ny, nx entries)
     int32_t nz, ny, nx, px;
     int32_t zc;           // planes (rows in 2D) per block
-    int16_t vx;           // cells per lane along x (2D tile width 64 * vx)
+    int16_t vx;           // 2D: cells per lane along x (tile width 64 * vx);
+                          // 3D: tile width / 64 (FP32: 4 or 2, the kernel)
     int16_t zghost;       // 3D FP32: planes of cur readable past each z end (the
                           // ghost planes of a z-slab), else 0 (zero edges)
     int32_t tiles_x, tiles_y, tiles_z;
