@@ -1000,22 +1000,26 @@ constexpr int k3dVX32 = FD_3D_VX32, k3dRY32 = FD_3D_RY32;   // FP32 fields
 constexpr int k3dVX16 = FD_3D_VX16, k3dRY16 = FD_3D_RY16;   // 16-bit fields
 constexpr int kBatchVX = 2;
 
-// FP32 fields have two tile shapes: 256x8 (4 cells x 2 rows per lane, the
-// faster where it fits) and 128x8 (4 cells x 1 row per lane, two rows per
-// wave), for grids whose x size leaves much of the last 256-wide tile
-// empty.  Measured per step (same bits): 384^3 210 -> 155 us, 320x512x512
-// 328 -> 248, 640x640x256 358 -> 310, 896x448x256 331 -> 305; 512^3 369
-// against 390 with the narrow tile, which costs about 5.5% per column.
+// FP32 fields have two tile shapes: 256x8 (4 cells x 2 rows per lane, 2
+// waves per SIMD) and 128x8 (4 cells x 1 row per lane, two rows per wave, 3
+// waves per SIMD).  The wide tile is faster on large grids that it fits
+// (512^3 369 against 390 us, 768x768x512 860 against 925: about 5.5% per
+// column), the narrow one where the x size leaves much of the last 256-wide
+// tile empty (384^3 210 -> 155 us, 320x512x512 328 -> 248, 640x640x256 358
+// -> 310, 896x448x256 331 -> 305) and on small grids, which need short
+// z-chunks to fill the device and gain from twice the columns (256^3 55 ->
+// 51 us, 768x256x256 140 -> 135); same bits either way.
 constexpr int k3dRYN32 = 1, k3dRPWN32 = 2;
 constexpr int k3dTXW32 = 64 / FD_3D_RPW32 * k3dVX32, k3dTXN32 = 64 / k3dRPWN32 * k3dVX32;
 
-// Whether an FP32 3D step of nx cells per row takes the narrow tile: when
-// its padded width, at 1.055 times the cost per column, is smaller.
-static bool narrow_tile_f32(int nx)
+// Whether an FP32 3D step takes the narrow tile: when its padded width, at
+// 1.055 times the cost per column, is smaller, or when the grid (at the
+// wide tile's padded width) holds fewer than 2^26 cells.
+static bool narrow_tile_f32(int nx, int ny, int nz)
 {
     const int64_t wide = ((int64_t)nx + k3dTXW32 - 1) / k3dTXW32 * k3dTXW32;
     const int64_t narrow = ((int64_t)nx + k3dTXN32 - 1) / k3dTXN32 * k3dTXN32;
-    return 1000 * wide > 1055 * narrow;
+    return 1000 * wide > 1055 * narrow || wide * ny * nz < ((int64_t)1 << 26);
 }
 
 // The 3D forward kernel of a storage kind (16-bit c or not; FP32: the
@@ -1077,7 +1081,7 @@ void plan_tiles(StepArgs &a, int ndim, int storage, bool batched)
     } else {
         // 3D: a.vx records the tile width in units of 64 cells, which picks
         // the FP32 kernel (4: 256 wide, 2: 128 wide)
-        const bool narrow = storage == kF32 && narrow_tile_f32(a.nx);
+        const bool narrow = storage == kF32 && narrow_tile_f32(a.nx, a.ny, a.nz);
         const int VX = storage == kF32 ? k3dVX32 : k3dVX16;
         const int RY = storage == kF32 ? (narrow ? k3dRYN32 : k3dRY32) : k3dRY16;
         const int NW = storage == kF32 ? FD_3D_NW32 : FD_3D_NW16;
