@@ -969,9 +969,10 @@ hipError_t launch_grad_finish(const double *g, const float *c, double *grad_v, i
 
 // Tile shapes.  2D: one wave, 64*VX columns by zc rows.  3D: NW waves of
 // RPW rows each, (64/RPW*VX) x (NW*RPW*RY) cells by zc planes: FP32 fields
-// 256x8 (4 cells x 2 rows per lane), 16-bit fields 128x8 (4 cells x 1 row per
-// lane, two rows per wave: half the y-halo loads of a 256x4 tile, measured
-// 568 -> 554 us at 768x768x512 BF16).  (Overridable at build time for tuning.)
+// 256x8 (4 cells x 2 rows per lane) or, chosen per grid, 128x8 (below),
+// 16-bit fields 128x8 (4 cells x 1 row per lane, two rows per wave: half the
+// y-halo loads of a 256x4 tile, measured 568 -> 554 us at 768x768x512 BF16).
+// (Overridable at build time for tuning.)
 #ifndef FD_3D_VX32
 #define FD_3D_VX32 4
 #endif
@@ -1061,7 +1062,8 @@ static int64_t resident_blocks_3d(int storage, bool cq, bool narrow)
 
 // Tile shapes.  3D: NW waves of RPW rows, (64/RPW VX) x (NW RPW RY) cells by
 // zc planes (the defaults come from a sweep of shapes on the 512^3 and
-// 768x768x512 grids).
+// 768x768x512 grids; FP32 grids pick the wide or the narrow tile with
+// narrow_tile_f32).
 // 2D: one wave, 64 VX columns by zc rows; the widest tile and tallest chunk
 // that still give >= 2048 blocks (8 per CU) are taken from
 // (VX, zc) = (2, 16), (2, 8), (1, 8), (1, 4).
