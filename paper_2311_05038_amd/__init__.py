@@ -39,6 +39,34 @@ def _stream_handle(stream: Optional[torch.cuda.Stream] = None) -> int:
     return int(s.cuda_stream)
 
 
+def _buf(t: torch.Tensor, what: str, dtype, numel: int) -> int:
+    """Address of a caller's device tensor after checking that it can hold
+    what the library reads or writes there (the C calls take raw pointers
+    and cannot): a contiguous CUDA tensor of `dtype` with at least `numel`
+    elements."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise ValueError(f"{what} must be a device tensor")
+    if t.dtype != dtype or not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous {dtype}")
+    if t.numel() < numel:
+        raise ValueError(f"{what} holds {t.numel()} elements, {numel} are needed")
+    return t.data_ptr()
+
+
+def _same_len(shots, **lists) -> None:
+    """The multi-shot calls read one entry of each array per shot."""
+    for name, v in lists.items():
+        if v is not None and len(v) != len(shots):
+            raise ValueError(f"{name} has {len(v)} entries for {len(shots)} shots")
+
+
+def _nbytes(t: torch.Tensor) -> int:
+    """Size in bytes of a caller's device buffer (any element type)."""
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or not t.is_contiguous():
+        raise ValueError("buffers must be contiguous device tensors")
+    return t.numel() * t.element_size()
+
+
 def _alloc(nbytes: int, device) -> torch.Tensor:
     """A 256-byte aligned device byte buffer (torch's caching allocator
     returns at least 512-byte aligned blocks)."""
@@ -165,10 +193,10 @@ class Model:
         if traces is None:
             traces = torch.empty((shot.nt, shot.nrec), dtype=torch.float32,
                                  device=self.device)
-        _abi.fd_run_shot(self.handle, state.handle, shot._c,
-                         traces.data_ptr() if shot.nrec > 0 else None,
+        tp = _buf(traces, "traces", torch.float32, shot.nt * shot.nrec) if shot.nrec > 0 else None
+        _abi.fd_run_shot(self.handle, state.handle, shot._c, tp,
                          ckpt.data_ptr() if ckpt is not None else None,
-                         ckpt.numel() if ckpt is not None else 0, ckpt_every,
+                         _nbytes(ckpt) if ckpt is not None else 0, ckpt_every,
                          _stream_handle(stream))
         state.next = shot.nt
         return traces
@@ -179,16 +207,16 @@ class Model:
     def adjoint_gradient(self, shot: Shot, adj: torch.Tensor, ckpt: torch.Tensor,
                          ckpt_every: int, grad_v: torch.Tensor,
                          work: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
-        if adj.dtype != torch.float32 or not adj.is_contiguous():
-            raise ValueError("adj must be contiguous FP32")
+        ap = _buf(adj, "adj", torch.float32, shot.nt * shot.nrec)
         if grad_v.dtype != torch.float64 or grad_v.numel() != self.grid.ncells:
             raise ValueError("grad_v must be an FP64 tensor of the grid's size")
+        gp = _buf(grad_v, "grad_v", torch.float64, self.grid.ncells)
         need = self.sizes_for(shot.nt, ckpt_every).adjoint_work
         if work is None:
             work = _alloc(need, self.device)
-        _abi.fd_adjoint_gradient(self.handle, shot._c, adj.data_ptr(), ckpt.data_ptr(),
-                                 ckpt.numel(), ckpt_every, work.data_ptr(), work.numel(),
-                                 grad_v.data_ptr(), _stream_handle(stream))
+        _abi.fd_adjoint_gradient(self.handle, shot._c, ap, ckpt.data_ptr(),
+                                 _nbytes(ckpt), ckpt_every, work.data_ptr(), _nbytes(work),
+                                 gp, _stream_handle(stream))
         return grad_v
 
     def rtm_image(self, shot: Shot, data: torch.Tensor, ckpt: torch.Tensor, ckpt_every: int,
@@ -197,15 +225,15 @@ class Model:
         """fd_rtm_image: image += sum_k z^k w^{k-1} for the receiver field
         back-propagated from `data` ([nt][nrec] FP32) and the source field
         recomputed from `ckpt` (saved by run_shot with the same ckpt_every)."""
-        if data.dtype != torch.float32 or not data.is_contiguous():
-            raise ValueError("data must be contiguous FP32")
+        dp = _buf(data, "data", torch.float32, shot.nt * shot.nrec)
         if image.dtype != torch.float64 or image.numel() != self.grid.ncells:
             raise ValueError("image must be an FP64 tensor of the grid's size")
+        ip = _buf(image, "image", torch.float64, self.grid.ncells)
         need = self.sizes_for(shot.nt, ckpt_every).adjoint_work
         if work is None:
             work = _alloc(need, self.device)
-        _abi.fd_rtm_image(self.handle, shot._c, data.data_ptr(), ckpt.data_ptr(), ckpt.numel(),
-                          ckpt_every, work.data_ptr(), work.numel(), image.data_ptr(),
+        _abi.fd_rtm_image(self.handle, shot._c, dp, ckpt.data_ptr(), _nbytes(ckpt),
+                          ckpt_every, work.data_ptr(), _nbytes(work), ip,
                           _stream_handle(stream))
         return image
 
@@ -218,29 +246,33 @@ class Model:
         checkpoint buffer); traces [nshots, nt, nrec]."""
         nt = shots[0].nt
         nrec = shots[0].nrec
+        if any(s.nt != nt or s.nrec != nrec for s in shots):
+            raise ValueError("the shots must share nt and the receiver count")
+        _same_len(shots, states=states, ckpts=ckpts)
         if traces is None:
             traces = torch.empty((len(shots), nt, nrec), dtype=torch.float32, device=self.device)
+        base = _buf(traces, "traces", torch.float32, len(shots) * nt * nrec) if nrec > 0 else 0
         _abi.fd_run_shots(self.handle, [st.handle for st in states], [s._c for s in shots],
-                          [traces[i].data_ptr() if s.nrec > 0 else None for i, s in enumerate(shots)],
+                          [base + 4 * i * nt * nrec if s.nrec > 0 else None for i, s in enumerate(shots)],
                           [c.data_ptr() for c in ckpts] if ckpts is not None else None,
-                          ckpts[0].numel() if ckpts is not None else 0, ckpt_every,
+                          min(_nbytes(c) for c in ckpts) if ckpts is not None else 0, ckpt_every,
                           _stream_handle(stream))
         for st in states:
             st.next = nt
         return traces
 
     def _backward_shots(self, fn, shots, srcs, ckpts, ckpt_every, out, works, stream):
-        for t in srcs:
-            if t.dtype != torch.float32 or not t.is_contiguous():
-                raise ValueError("adjoint sources must be contiguous FP32")
+        _same_len(shots, sources=srcs, ckpts=ckpts, works=works)
+        ptrs = [_buf(t, "adjoint source", torch.float32, sh.nt * sh.nrec) for t, sh in zip(srcs, shots)]
         if out.dtype != torch.float64 or out.numel() != self.grid.ncells:
             raise ValueError("the output must be an FP64 tensor of the grid's size")
+        op = _buf(out, "the output", torch.float64, self.grid.ncells)
         need = self.sizes_for(shots[0].nt, ckpt_every).adjoint_work
         if works is None:
             works = [_alloc(need, self.device) for _ in shots]
-        fn(self.handle, [s._c for s in shots], [t.data_ptr() for t in srcs],
-           [c.data_ptr() for c in ckpts], ckpts[0].numel(), ckpt_every,
-           [w.data_ptr() for w in works], works[0].numel(), out.data_ptr(), _stream_handle(stream))
+        fn(self.handle, [s._c for s in shots], ptrs,
+           [c.data_ptr() for c in ckpts], min(_nbytes(c) for c in ckpts), ckpt_every,
+           [w.data_ptr() for w in works], min(_nbytes(w) for w in works), op, _stream_handle(stream))
         return out
 
     def adjoint_gradient_shots(self, shots: Sequence[Shot], adj: Sequence[torch.Tensor],
@@ -279,14 +311,20 @@ class State:
         self.handle = _abi.fd_create_state(model.handle, self.buf.data_ptr(), model.sizes.state)
         self.next = -1
 
+    @staticmethod
+    def _row(trace_row: Optional[torch.Tensor], shot: Shot):
+        """Address of one step's trace row (nrec FP32 values), or None."""
+        if trace_row is None or shot.nrec == 0:
+            return None
+        return _buf(trace_row, "trace_row", torch.float32, shot.nrec)
+
     def begin(self, shot: Shot, stream=None) -> None:
         _abi.fd_begin_shot(self.model.handle, self.handle, shot._c, _stream_handle(stream))
         self.next = 0
 
     def step(self, shot: Shot, n: int, trace_row: Optional[torch.Tensor] = None,
              stream=None) -> None:
-        _abi.fd_step(self.model.handle, self.handle, shot._c, n,
-                     trace_row.data_ptr() if trace_row is not None else None,
+        _abi.fd_step(self.model.handle, self.handle, shot._c, n, self._row(trace_row, shot),
                      _stream_handle(stream))
         self.next = n + 1
 
@@ -294,10 +332,8 @@ class State:
                       trace_row: Optional[torch.Tensor] = None, stream=None) -> None:
         """Step n as one kernel per routine (fd_step_routines); `work` is a
         device byte buffer of at least Model.sizes.routines_work bytes."""
-        _abi.fd_step_routines(self.model.handle, self.handle, shot._c, n,
-                              trace_row.data_ptr() if trace_row is not None else None,
-                              work.data_ptr(), work.numel() * work.element_size(),
-                              _stream_handle(stream))
+        _abi.fd_step_routines(self.model.handle, self.handle, shot._c, n, self._row(trace_row, shot),
+                              work.data_ptr(), _nbytes(work), _stream_handle(stream))
         self.next = n + 1
 
     def step_routines_noalloc(self, shot: Shot, n: int, trace_row: Optional[torch.Tensor] = None,
@@ -306,8 +342,7 @@ class State:
         area (fd_step_routines_noalloc): no buffer is allocated or passed;
         grids whose routine work exceeds the area raise FDError."""
         _abi.fd_step_routines_noalloc(self.model.handle, self.handle, shot._c, n,
-                                      trace_row.data_ptr() if trace_row is not None else None,
-                                      _stream_handle(stream))
+                                      self._row(trace_row, shot), _stream_handle(stream))
         self.next = n + 1
 
     def check_finite(self, flags: Optional[torch.Tensor] = None, stream=None) -> torch.Tensor:
@@ -317,7 +352,7 @@ class State:
         to reuse a buffer."""
         if flags is None:
             flags = torch.empty(1, dtype=torch.int32, device=self.model.device)
-        _abi.fd_check_finite(self.handle, flags.data_ptr(), _stream_handle(stream))
+        _abi.fd_check_finite(self.handle, _buf(flags, "flags", torch.int32, 1), _stream_handle(stream))
         return flags
 
     def is_finite(self, stream=None) -> bool:
@@ -329,14 +364,17 @@ class State:
         if out is None:
             out = torch.empty(self.model.grid.shape, dtype=torch.float32,
                               device=self.model.device)
-        _abi.fd_get_wavefield(self.handle, which, out.data_ptr(), _stream_handle(stream))
+        _abi.fd_get_wavefield(self.handle, which, _buf(out, "out", torch.float32, self.model.grid.ncells),
+                              _stream_handle(stream))
         return out
 
     def set_wavefield(self, which: int, values: torch.Tensor, stream=None) -> None:
         if values.dtype != torch.float32 or values.numel() != self.model.grid.ncells:
             raise ValueError("values must be FP32 with one entry per cell")
         values = values.contiguous()
-        _abi.fd_set_wavefield(self.handle, which, values.data_ptr(), _stream_handle(stream))
+        _abi.fd_set_wavefield(self.handle, which,
+                              _buf(values, "values", torch.float32, self.model.grid.ncells),
+                              _stream_handle(stream))
         if self.next < 0:
             self.next = 0
 
@@ -361,12 +399,9 @@ class ShotGraph:
                  traces: Optional[torch.Tensor] = None):
         if traces is None:
             traces = torch.empty((shot.nt, shot.nrec), dtype=torch.float32, device=model.device)
-        if shot.nrec and (traces.dtype != torch.float32 or not traces.is_contiguous()
-                          or traces.numel() < shot.nt * shot.nrec):
-            raise ValueError("traces must be contiguous FP32 with nt x nrec entries")
+        tp = _buf(traces, "traces", torch.float32, shot.nt * shot.nrec) if shot.nrec > 0 else None
         self.model, self.state, self.shot, self.traces = model, state, shot, traces
-        self.handle = _abi.fd_shot_graph_create(model.handle, state.handle, shot._c,
-                                                traces.data_ptr() if shot.nrec > 0 else None)
+        self.handle = _abi.fd_shot_graph_create(model.handle, state.handle, shot._c, tp)
 
     def launch(self, stream=None) -> torch.Tensor:
         _abi.fd_shot_graph_launch(self.handle, _stream_handle(stream))
@@ -402,7 +437,8 @@ def step_batch(entries: Sequence[tuple], nsteps: int, stream=None) -> list:
         arr[i].shot = ctypes.pointer(shot._c)
         keep.append(arr[i].shot)
         arr[i].n = state.next
-        arr[i].traces = traces.data_ptr() if traces is not None else None
+        arr[i].traces = (_buf(traces, "traces", torch.float32, shot.nt * shot.nrec)
+                         if traces is not None and shot.nrec > 0 else None)
     if entries:
         _abi.check(_abi.lib().fd_step_batch(arr, len(entries), nsteps, _stream_handle(stream)))
     out = []

@@ -181,3 +181,17 @@ def test_last_error_is_per_thread():
     for t in ts:
         t.join()
     assert all(v == "ok" for v in seen.values()) and len(seen) == 8, seen
+
+
+def test_binding_buffer_checks_on_host():
+    """The binding's buffer check refuses host tensors, the wrong element
+    type, non-contiguous views and short tensors (no device needed)."""
+    import torch
+    import paper_2311_05038_amd as fd
+    with pytest.raises(ValueError, match="device tensor"):
+        fd._buf(torch.zeros(8), "x", torch.float32, 8)
+    with pytest.raises(ValueError, match="device tensor"):
+        fd._nbytes(torch.zeros(8))
+    with pytest.raises(ValueError, match="entries"):
+        fd._same_len([1, 2], states=[1])
+    fd._same_len([1, 2], states=[1, 2], ckpts=None)
