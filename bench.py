@@ -327,7 +327,7 @@ def summarize_serving_trace(kt_dir: str, requests: int):
     lines = [f"# Batched serving ({requests} Poisson 2D shots at 50/s): GPU busy time", "",
              "Kernel trace:", "",
              "    cd /tmp && export TMPDIR=/tmp",
-             f"    rocprofv3 --kernel-trace -T -f csv -d gpurun_out/prof/serve -o sv -- {cmd}", "",
+             f"    rocprofv3 --kernel-trace -T -f csv -d {kt_dir} -o sv -- {cmd}", "",
              "The window runs from the end of the first serving marker (a "
              f"{SERVE_MARK_N // 4}-thread fd_stream_probe launch) to the start of the second, "
              "around the batched run of the 50/s stream.", "",
@@ -338,7 +338,7 @@ def summarize_serving_trace(kt_dir: str, requests: int):
              "| kernel | launches | total s | avg us |", "|---|---|---|---|"]
     for n, t in tot.most_common(8):
         lines.append(f"| {n} | {cnt[n]} | {t / 1e9:.3f} | {t / cnt[n] / 1e3:.1f} |")
-    lines += ["", f"Summary written by `python bench.py --summarize-serving-trace gpurun_out/prof/serve "
+    lines += ["", f"Summary written by `python bench.py --summarize-serving-trace {kt_dir} "
                   f"--serve-requests {requests}`.", ""]
     with open(os.path.join(ROOT, "profiles", "k_step2d_batch_serving.md"), "w") as fh:
         fh.write("\n".join(lines))
@@ -752,7 +752,7 @@ def summarize_profiles(kt_dir: str, fetch_dir: str, write_dir: str, kernel: str 
 Kernel trace:
 
     cd /tmp && export TMPDIR=/tmp
-    rocprofv3 --kernel-trace --stats -T -f csv -d gpurun_out/prof/kt -o kt -- {cmd}
+    rocprofv3 --kernel-trace --stats -T -f csv -d {kt_dir} -o kt -- {cmd}
 
 {chr(10).join(lines)}
 
@@ -762,8 +762,8 @@ i.e. {100 * alg / (avg * 1e-6) / 8e12:.1f}% of the 8 TB/s HBM peak.
 
 Byte counters (one pass each):
 
-    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex "k_step3d|k_stream" -T -f csv -d gpurun_out/prof/fetch -o f -- {cmd}
-    rocprofv3 --pmc WRITE_SIZE --kernel-include-regex "k_step3d|k_stream" -T -f csv -d gpurun_out/prof/write -o w -- {cmd}
+    rocprofv3 --pmc FETCH_SIZE --kernel-include-regex "k_step3d|k_stream" -T -f csv -d {fetch_dir} -o f -- {cmd}
+    rocprofv3 --pmc WRITE_SIZE --kernel-include-regex "k_step3d|k_stream" -T -f csv -d {write_dir} -o w -- {cmd}
 
 | kernel | FETCH_SIZE KiB/dispatch | WRITE_SIZE KiB/dispatch | dispatches |
 |---|---|---|---|
@@ -776,7 +776,7 @@ WRITE_SIZE x {wscale:.3f}.  Scaled traffic per k_step3d launch:
 = {traffic / 1e9:.3f} GB vs {alg / 1e9:.3f} GB algorithmic ({traffic / alg:.3f}x).
 FETCH_SIZE counts L2 misses, including those the Infinity Cache serves.
 
-Summary written by `python bench.py --summarize-profiles gpurun_out/prof/kt gpurun_out/prof/fetch gpurun_out/prof/write`.
+Summary written by `python bench.py --summarize-profiles {kt_dir} {fetch_dir} {write_dir}`.
 """
     with open(os.path.join(ROOT, "profiles", "k_step3d_f32_layered3d_512.md"), "w") as fh:
         fh.write(md)
