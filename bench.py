@@ -217,7 +217,7 @@ def half_leg(nt: int = 2000):
         torch.cuda.empty_cache()
     for name in ("f16", "bf16", "f16_c16", "bf16_c16"):
         out["speedup_" + name] = round(out[name]["mcell_per_s"] / out["f32"]["mcell_per_s"], 3)
-    out["workload"] = "precision3d 768x768x512, nt=2000"
+    out["workload"] = f"precision3d 768x768x512, nt={nt}"
     return out
 
 
@@ -795,6 +795,8 @@ def main():
                     help="comma list of extra legs (half, adjoint, serve, routines, slab, small2d, "
                          "cpu) or 'none'")
     ap.add_argument("--serve-requests", type=int, default=1000)
+    ap.add_argument("--half-nt", type=int, default=2000,
+                    help="steps per shot of the 16-bit leg (a few for counter runs)")
     ap.add_argument("--summarize-profiles", nargs=3, metavar=("KT_DIR", "FETCH_DIR", "WRITE_DIR"),
                     help="write profiles/ summaries from rocprofv3 CSV output (host only)")
     ap.add_argument("--summarize-serving-trace", metavar="KT_DIR",
@@ -836,7 +838,7 @@ def main():
     legs = [x for x in args.legs.split(",") if x and x != "none"]
     extra = {}
     if "half" in legs:
-        extra["half_storage"] = half_leg()
+        extra["half_storage"] = half_leg(args.half_nt)
     if "adjoint" in legs:
         extra["adjoint"] = adjoint_leg()
     if "serve" in legs:
