@@ -136,26 +136,13 @@ __device__ __forceinline__ float decode(typename Stor<ST>::T q, float scale)
     }
 }
 
-// binary16 code -> FP32 value times 2^-112, by moving the sign to bit 31 and
-// the 15 exponent/significand bits to bits 13..27.  Exact for every finite
-// code, subnormals included (FP32 keeps subnormals here).
-__device__ __forceinline__ float f16_bits_scaled(uint16_t q)
-{
-    const uint32_t u = q;
-    return __uint_as_float(((u & 0x8000u) << 16) | ((u & 0x7FFFu) << 13));
-}
-
 // Decode used inside the step kernels, before the power-of-two field scale:
-// FP32 and bfloat16 exactly, binary16 times 2^-112 by the bit move (the
-// 2^112 goes into the update's coefficients; the hardware conversion
-// measured slower in the step kernel).
+// exact for every code (the hardware conversion for binary16, subnormals and
+// non-finite codes included; a shift for bfloat16).
 template <int ST>
 __device__ __forceinline__ float decode_raw(typename Stor<ST>::T q)
 {
-    if constexpr (ST == kF16)
-        return f16_bits_scaled(q);
-    else
-        return decode<ST>(q, 1.0f);
+    return decode<ST>(q, 1.0f);
 }
 
 // Round-to-nearest-even encode of x * inv_scale.
@@ -216,11 +203,11 @@ __device__ __forceinline__ int storage_exponent(float m)
 
 // Per-launch quantities of the 16-bit storage form.  The step computes the
 // new field directly in its storage units (value times 2^-en): the decode
-// scales of cur and prev are multiplied by the encode scale 2^-en (and, for
-// binary16 codes decoded by bit move, by 2^112), which is exact for powers
-// of two, so rounding the result to 16 bits needs no further multiply.
+// scales of cur and prev are multiplied by the encode scale 2^-en, which is
+// exact for powers of two, so rounding the result to 16 bits needs no
+// further multiply.
 struct HalfCtx {
-    float sc, sp;   // 2^(ec - en) [* 2^112], 2^(ep - en) [* 2^112]
+    float sc, sp;   // 2^(ec - en), 2^(ep - en)
     float sn;       // 2^en: storage units -> value (traces, magnitude)
     float sn_inv;   // 2^-en: value -> storage units (source term)
 };
@@ -246,9 +233,8 @@ __device__ __forceinline__ HalfCtx half_prologue(const StepArgs &a, float inj, b
         const int en = storage_exponent(m);
         // ec - en and ep - en stay within a few units (the magnitude changes
         // by a bounded factor per step); the clamp only keeps 2^k finite.
-        const int bias = ST == kF16 ? 112 : 0;
-        h.sc = pow2i(min(ec - en + bias, 127));
-        h.sp = pow2i(min(ep - en + bias, 127));
+        h.sc = pow2i(min(ec - en, 127));
+        h.sp = pow2i(min(ep - en, 127));
         h.sn = pow2i(en);
         h.sn_inv = pow2i(-en);
         if (block0) {

@@ -166,8 +166,8 @@ __device__ __forceinline__ void finish_cells(const StepArgs &a, const HalfCtx &h
 // The same update on 16-bit fields read as raw codes q (P = 2^ec q, Pold =
 // 2^ep qp, and L q computed from the raw q), producing the new field in its
 // storage units 2^-en: (G sc)(2 q + c L q) - (G^2 sp) qp with sc = 2^(ec-en)
-// and sp = 2^(ep-en) (times 2^112 for bit-moved binary16 codes).  This is the
-// scaled arithmetic exactly, since multiplying by 2^k does not round.
+// and sp = 2^(ep-en).  This is the scaled arithmetic exactly, since
+// multiplying by 2^k does not round.
 template <int ST>
 __device__ __forceinline__ float update(float G, float ctr, float c, float lap, float prev,
                                         const HalfCtx &h)
@@ -370,8 +370,8 @@ __global__ __launch_bounds__(64) void k_step2d_batch(Batch2D b)
 // waves stack NW*RPW rows, and each thread handles RY such row groups.
 // CQ: c is read as 16-bit fixed-point codes q (16-bit fields, forward step):
 // 2 P + c L P = s (2 P / s + q L P) with s = 2^(e-16), and s joins the
-// other power-of-two factors of the update (exact; the Laplacian keeps its
-// scale, which stays clear of FP32 subnormals with bit-moved binary16).
+// other power-of-two factors of the update (exact; the Laplacian keeps the
+// scale of the stored codes).
 template <int ST, int VX, int RY, int NW, int RPW, int MODE, bool CQ>
 __global__ __launch_bounds__(64 * NW) void k_step3d(StepArgs a)
 {
