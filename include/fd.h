@@ -336,14 +336,13 @@ fd_status fd_set_wavefield(fd_state *state, int32_t which, const float *in, void
  * non-finite value entered the shot (one of the nt values amp * s[n] the
  * shot injects, found when fd_begin_shot runs, or a value given to
  * fd_set_wavefield); 0 for a healthy shot.  Stream-ordered like the steps,
- * so after fd_run_shot it reports on the finished shot.  With FP32 and
- * bfloat16 fields a non-finite value never becomes finite again under the
- * update of Eq. 1 (it, or a non-finite stencil neighbour, makes the new
- * value non-finite, and the grid's edges and padding hold zeros), so bits 0
- * and 1 after the last step cover every step, overflow included; binary16
- * fields decode a non-finite code to a large finite value at the next step,
- * where bit 2 covers the inputs (their storage scale keeps 16x headroom, so
- * the scheme itself cannot overflow them).  A shot corrupted this way is
+ * so after fd_run_shot it reports on the finished shot.  A non-finite value
+ * never becomes finite again under the update of Eq. 1 (it, or a non-finite
+ * stencil neighbour, makes the new value non-finite; the grid's edges and
+ * padding hold zeros; 16-bit codes decode exactly, non-finite ones
+ * included), so bits 0 and 1 after the last step cover every step, overflow
+ * included (16-bit fields keep 16x headroom in their storage scale, so the
+ * scheme itself cannot overflow them).  A shot corrupted this way is
  * reported here instead of ending with FD_OK and meaningless traces.  Cost:
  * one read of the two levels (8 bytes per cell with FP32 fields).  Errors:
  * FD_ERR_INVALID_ARG for NULL or misaligned arguments or a state that has

@@ -1,9 +1,8 @@
 """fd_check_finite on the GPU: a healthy shot reports 0; a NaN or an infinity
 planted in P through fd_set_wavefield is reported at once (bit 0 for the
 level, bit 2 for the non-finite input) and, after more steps, in both levels
-(bits 0 and 1) with FP32 and bfloat16 fields, where non-finite values
-persist, while binary16 fields keep bit 2 (their bit-move decode reads a
-non-finite code as a large finite value); 2D and 3D, and a z-slab; a
+(bits 0 and 1) with every storage kind, where non-finite values persist
+(16-bit codes decode exactly, non-finite ones included); 2D and 3D, and a z-slab; a
 non-finite wavelet sample sets bit 2 at fd_begin_shot; in the shot server, a
 shot whose wavelet carries a NaN fails alone while the other shots of the mix
 finish with the bits they have alone.  Nothing here makes a kernel fault: the
@@ -39,7 +38,7 @@ def test_planted_nonfinite_is_reported(storage, ndim, bad):
     for n in range(6, 12):
         st.step(shot, n)
     flags = int(st.check_finite().item())
-    assert flags == 7 if storage != 1 else flags & 4
+    assert flags == 7
     assert not st.is_finite()
     # a fresh shot clears the flags; a non-finite wavelet sample sets bit 2
     st.begin(shot)
